@@ -1,0 +1,301 @@
+"""Plain FP64 CPU oracle for the SEM Helmholtz hot path (arXiv 2107.01243).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``; never by the product package.
+It shares no code with the HIP path.  The arithmetic lives in
+``sem_oracle.c`` (plain loops, FP64, ``-O2 -ffp-contract=off``); this module
+only marshals numpy arrays into it.
+
+Every function cites the passage of the paper it follows; the readings taken
+where the paper is silent or garbled are listed at the top of ``sem_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sem_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile sem_oracle.c into liboracle.so with gcc (FP64, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+               "-shared", "-std=c11", "-D_GNU_SOURCE", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        vp = C.c_void_p
+        L.orc_gll.argtypes = [C.c_int, _f64p, _f64p]
+        L.orc_deriv_matrix.argtypes = [C.c_int, _f64p, _f64p]
+        L.orc_box_mesh.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _f64p,
+                                   _i64p, _u8p, _f64p, _f64p, _f64p]
+        L.orc_box_mesh.restype = None
+        L.orc_geometry.argtypes = [C.c_int64, C.c_int, _f64p, _f64p, _f64p, _f64p, _f64p,
+                                   _f64p, _f64p, _f64p]
+        L.orc_geometry.restype = C.c_int64
+        L.orc_ax_helm.argtypes = [C.c_int64, C.c_int, _f64p, _f64p, vp, vp, C.c_double,
+                                  vp, C.c_double, _f64p, _f64p]
+        L.orc_ax_helm.restype = None
+        L.orc_ax_adjoint.argtypes = [C.c_int64, C.c_int, _f64p, _f64p, _f64p, _f64p, _f64p]
+        L.orc_ax_adjoint.restype = None
+        L.orc_gs_create.argtypes = [C.c_int64, _i64p]
+        L.orc_gs_create.restype = vp
+        L.orc_gs_ngroups.argtypes = [vp]
+        L.orc_gs_ngroups.restype = C.c_int64
+        L.orc_gs_nentries.argtypes = [vp]
+        L.orc_gs_nentries.restype = C.c_int64
+        L.orc_gs_groups.argtypes = [vp, _i64p, _i64p, _i64p]
+        L.orc_gs_groups.restype = None
+        L.orc_gs_op.argtypes = [vp, _f64p]
+        L.orc_gs_op.restype = None
+        L.orc_gs_free.argtypes = [vp]
+        L.orc_gs_free.restype = None
+        L.orc_multiplicity.argtypes = [vp, _f64p]
+        L.orc_multiplicity.restype = None
+        L.orc_apply.argtypes = [C.c_int64, C.c_int, _f64p, _f64p, vp, vp, C.c_double, vp,
+                                C.c_double, vp, vp, _f64p, _f64p]
+        L.orc_apply.restype = None
+        L.orc_diag.argtypes = [C.c_int64, C.c_int, _f64p, _f64p, vp, vp, C.c_double, vp,
+                               C.c_double, _f64p]
+        L.orc_diag.restype = None
+        L.orc_jacobi_dinv.argtypes = [C.c_int64, C.c_int, _f64p, _f64p, vp, vp, C.c_double,
+                                      vp, C.c_double, vp, vp, _f64p]
+        L.orc_jacobi_dinv.restype = None
+        L.orc_wdot.argtypes = [C.c_int64, _f64p, _f64p, _f64p]
+        L.orc_wdot.restype = C.c_double
+        L.orc_pcg.argtypes = [C.c_int64, C.c_int, _f64p, _f64p, vp, vp, C.c_double, vp,
+                              C.c_double, vp, vp, _f64p, _f64p, _f64p, C.c_double, C.c_int,
+                              C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.orc_pcg.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _coef(h):
+    """A coefficient is a python float (scalar) or an FP64 array of n_p values."""
+    if h is None:
+        return None, 0.0
+    if np.isscalar(h):
+        return None, float(h)
+    a = np.ascontiguousarray(h, dtype=np.float64)
+    return a, 0.0
+
+
+# ---------------------------------------------------------------- space
+def gll(lx: int):
+    """GLL points and weights (Section 2, Eq. 7-8)."""
+    xi = np.zeros(lx)
+    w = np.zeros(lx)
+    if lib().orc_gll(lx, xi, w) != 0:
+        raise ValueError(f"lx={lx} out of range")
+    return xi, w
+
+
+def deriv_matrix(xi):
+    """D[i, l] = l_l'(xi_i), the local derivative matrix of Eq. 9."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    D = np.zeros((len(xi), len(xi)))
+    lib().orc_deriv_matrix(len(xi), xi, D)
+    return D
+
+
+# ---------------------------------------------------------------- mesh
+def box_mesh(nx: int, ny: int, nz: int, lx: int, eps: float):
+    """Structured box mesh on [0,1]^3, curved by the smooth sine map of amplitude eps.
+
+    Returns dict with glb (int64), dirichlet (uint8), x, y, z (FP64), all n_p long.
+    """
+    xi, _ = gll(lx)
+    n = nx * ny * nz * lx ** 3
+    glb = np.zeros(n, np.int64)
+    dr = np.zeros(n, np.uint8)
+    x = np.zeros(n)
+    y = np.zeros(n)
+    z = np.zeros(n)
+    lib().orc_box_mesh(nx, ny, nz, lx, float(eps), xi, glb, dr, x, y, z)
+    return dict(glb=glb, dirichlet=dr, x=x, y=y, z=z)
+
+
+def geometry(lx: int, D, w, x, y, z):
+    """Geometric factors G (6, n_p: G11, G22, G33, G12, G13, G23), B and J (Eq. 9)."""
+    n = len(x)
+    nelv = n // lx ** 3
+    G = np.zeros((6, n))
+    B = np.zeros(n)
+    J = np.zeros(n)
+    bad = lib().orc_geometry(nelv, lx, np.ascontiguousarray(D), np.ascontiguousarray(w),
+                             np.ascontiguousarray(x), np.ascontiguousarray(y),
+                             np.ascontiguousarray(z), G, B, J)
+    if bad:
+        raise ValueError(f"{bad} points with non-positive Jacobian")
+    return G, B, J
+
+
+# ---------------------------------------------------------------- operators
+def ax_helm(lx, D, G, B, u, h1=1.0, h2=0.0):
+    """Unassembled Helmholtz action w = A_L u (Eq. 9-10)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    n = len(u)
+    w = np.zeros(n)
+    h1a, h1s = _coef(h1)
+    h2a, h2s = _coef(h2)
+    Bc = None if B is None else np.ascontiguousarray(B, dtype=np.float64)
+    lib().orc_ax_helm(n // lx ** 3, lx, np.ascontiguousarray(D), np.ascontiguousarray(G),
+                      _ptr(Bc), _ptr(h1a), h1s, _ptr(h2a), h2s, u, w)
+    return w
+
+
+def ax_adjoint(lx, D, G, u, v):
+    """g_p = (D v)_p^T G_p (D u)_p = d(v^T A_L(h1) u)/d h1_p (h1-linearity of Eq. 9)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    g = np.zeros(len(u))
+    lib().orc_ax_adjoint(len(u) // lx ** 3, lx, np.ascontiguousarray(D),
+                         np.ascontiguousarray(G), u, v, g)
+    return g
+
+
+class GS:
+    """Gather-scatter QQ^T (Eq. 10, Algorithm 1 local part), canonical ascending order."""
+
+    def __init__(self, glb):
+        self.glb = np.ascontiguousarray(glb, dtype=np.int64)
+        self.n = len(self.glb)
+        self._h = lib().orc_gs_create(self.n, self.glb)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.orc_gs_free(self._h)
+            self._h = None
+
+    def groups(self):
+        """(off, idx, gid): groups of local indices sharing a global id with mult >= 2."""
+        ng = lib().orc_gs_ngroups(self._h)
+        ne = lib().orc_gs_nentries(self._h)
+        off = np.zeros(ng + 1, np.int64)
+        idx = np.zeros(max(ne, 1), np.int64)
+        gid = np.zeros(max(ng, 1), np.int64)
+        lib().orc_gs_groups(self._h, off, idx, gid)
+        return off, idx[:ne], gid[:ng]
+
+    def op(self, u):
+        """Return QQ^T u (a new array)."""
+        v = np.array(u, dtype=np.float64, copy=True)
+        lib().orc_gs_op(self._h, v)
+        return v
+
+    def mult(self):
+        m = np.zeros(self.n)
+        lib().orc_multiplicity(self._h, m)
+        return m
+
+
+def wdot(a, b, mult):
+    """Unique-node inner product sum_L a_L b_L / mult_L."""
+    return lib().orc_wdot(len(a), np.ascontiguousarray(a, dtype=np.float64),
+                          np.ascontiguousarray(b, dtype=np.float64),
+                          np.ascontiguousarray(mult, dtype=np.float64))
+
+
+class Problem:
+    """One discrete Helmholtz problem: space, mesh, geometry, gather-scatter, mask.
+
+    A = mask QQ^T A_L(h1, h2) in local layout (Eq. 9-10 with Eq. 5 imposed by masking).
+    """
+
+    def __init__(self, nx, lx, eps=0.0, h1=1.0, h2=0.0, ny=None, nz=None):
+        ny = nx if ny is None else ny
+        nz = nx if nz is None else nz
+        self.lx = lx
+        self.nelv = nx * ny * nz
+        self.n = self.nelv * lx ** 3
+        self.xi, self.w = gll(lx)
+        self.D = deriv_matrix(self.xi)
+        m = box_mesh(nx, ny, nz, lx, eps)
+        self.glb, self.dirichlet = m["glb"], m["dirichlet"]
+        self.x, self.y, self.z = m["x"], m["y"], m["z"]
+        self.G, self.B, self.J = geometry(lx, self.D, self.w, self.x, self.y, self.z)
+        self.gs = GS(self.glb)
+        self.mult = self.gs.mult()
+        self.set_coef(h1, h2)
+
+    def set_coef(self, h1, h2):
+        self.h1, self.h2 = h1, h2
+        self._h1a, self._h1s = _coef(h1)
+        self._h2a, self._h2s = _coef(h2)
+        self.dinv = np.zeros(self.n)
+        lib().orc_jacobi_dinv(self.nelv, self.lx, self.D, self.G, _ptr(self.B),
+                              _ptr(self._h1a), self._h1s, _ptr(self._h2a), self._h2s,
+                              self.gs._h, _ptr(self.dirichlet), self.dinv)
+
+    def ax_local(self, u):
+        return ax_helm(self.lx, self.D, self.G, self.B, u, self.h1, self.h2)
+
+    def apply(self, u):
+        """w = mask QQ^T A_L u."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        w = np.zeros(self.n)
+        lib().orc_apply(self.nelv, self.lx, self.D, self.G, _ptr(self.B), _ptr(self._h1a),
+                        self._h1s, _ptr(self._h2a), self._h2s, self.gs._h,
+                        _ptr(self.dirichlet), u, w)
+        return w
+
+    def diag_local(self):
+        d = np.zeros(self.n)
+        lib().orc_diag(self.nelv, self.lx, self.D, self.G, _ptr(self.B), _ptr(self._h1a),
+                       self._h1s, _ptr(self._h2a), self._h2s, d)
+        return d
+
+    def assemble_rhs(self, f_local):
+        """b = mask QQ^T f: a local load vector summed onto the unique nodes."""
+        b = self.gs.op(f_local)
+        b[self.dirichlet.astype(bool)] = 0.0
+        return b
+
+    def pcg(self, b, x0=None, rtol=1e-10, max_iter=100000):
+        """Jacobi-PCG (Section 4 velocity solver).  rtol <= 0: exactly max_iter steps."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        it = C.c_int(0)
+        rr = C.c_double(0.0)
+        st = lib().orc_pcg(self.nelv, self.lx, self.D, self.G, _ptr(self.B), _ptr(self._h1a),
+                           self._h1s, _ptr(self._h2a), self._h2s, self.gs._h,
+                           _ptr(self.dirichlet), self.dinv, b, x, float(rtol), int(max_iter),
+                           C.byref(it), C.byref(rr))
+        return x, dict(status=st, iters=it.value, rel_res=rr.value)
+
+    def dot(self, a, b):
+        return wdot(a, b, self.mult)
+
+    def true_rel_res(self, x, b):
+        r = b - self.apply(x)
+        return np.sqrt(self.dot(r, r)) / np.sqrt(self.dot(b, b))
+
+    def adjoint(self, u, v):
+        return ax_adjoint(self.lx, self.D, self.G, u, v)

@@ -1,0 +1,425 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle (``oracle/``) against something other than itself:
+closed forms, quadrature exactness, integer counts, exact identities of the
+discrete operator (Eq. 9-10), an independent dense numpy brute force
+(``tests/brute.py``), the continuous PDE (spectral convergence), and finite
+differences.  No GPU is needed.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import brute
+import oracle
+import workloads
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _ev(s):
+    return float(eval(s, {"sqrt": math.sqrt}))
+
+
+def _cont(P, seed, zero_dirichlet=False):
+    """A continuous local vector u_L = Q u_g with u_g ~ U[-1,1] per unique id."""
+    ug = workloads.uniform(int(P.glb.max()) + 1, seed)
+    u = ug[P.glb]
+    if zero_dirichlet:
+        u = np.where(P.dirichlet.astype(bool), 0.0, u)
+    return u
+
+
+# ------------------------------------------------------------------ GLL space (Eq. 7-8)
+def test_gll_closed_forms():
+    g = json.load(open(os.path.join(GOLD, "gll_closed_forms.json")))
+    for rule in g["rules"]:
+        xi, w = oracle.gll(rule["N"] + 1)
+        np.testing.assert_allclose(xi, [_ev(s) for s in rule["points"]], rtol=0, atol=2e-16)
+        np.testing.assert_allclose(w, [_ev(s) for s in rule["weights"]], rtol=0, atol=4e-16)
+
+
+@pytest.mark.parametrize("lx", range(2, 17))
+def test_gll_vs_numpy_moments(lx):
+    xi, w = oracle.gll(lx)
+    xb, wb = brute.gll(lx)
+    np.testing.assert_allclose(xi, xb, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(w, wb, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("lx", [3, 5, 8, 12, 16])
+def test_gll_exactness_degree(lx):
+    """GLL with N+1 points integrates x^k exactly for k <= 2N-1 and not for k = 2N."""
+    N = lx - 1
+    xi, w = oracle.gll(lx)
+    assert abs(w.sum() - 2.0) < 1e-14
+    for k in range(2 * N):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.dot(w, xi ** k) - exact) < 1e-13, k
+    k = 2 * N
+    assert abs(np.dot(w, xi ** k) - 2.0 / (k + 1)) > 1e-10
+
+
+def test_dmat_closed_form_N2():
+    g = json.load(open(os.path.join(GOLD, "gll_closed_forms.json")))["derivative_N2"]
+    D = oracle.deriv_matrix(oracle.gll(3)[0])
+    np.testing.assert_allclose(D, [[_ev(s) for s in row] for row in g["D"]], atol=1e-15)
+
+
+@pytest.mark.parametrize("lx", range(2, 17))
+def test_dmat_vs_vandermonde(lx):
+    xi, _ = oracle.gll(lx)
+    D = oracle.deriv_matrix(xi)
+    Db = brute.dmat(brute.gll(lx)[0])
+    assert np.abs(D - Db).max() <= 1e-11 * np.abs(Db).max()
+    # exact derivative of x^k for k <= N; rows sum to zero
+    for k in range(1, lx):
+        np.testing.assert_allclose(D @ xi ** k, k * xi ** (k - 1), atol=1e-12 * lx ** 2)
+    assert np.abs(D.sum(axis=1)).max() < 1e-12 * lx ** 2
+
+
+# ------------------------------------------------------------------ mesh and numbering
+def test_multiplicity_and_dirichlet_counts():
+    cases = json.load(open(os.path.join(GOLD, "box_mesh_counts.json")))["cases"]
+    for c in cases:
+        m = oracle.box_mesh(c["nx"], c["nx"], c["nx"], c["lx"], 0.05)
+        gs = oracle.GS(m["glb"])
+        mult = gs.mult()
+        for k in (1, 2, 4, 8):
+            assert int(np.sum(mult == k)) == k * c[f"mult{k}"], (c, k)
+        assert len(np.unique(m["glb"])) == c["unique"]
+        assert len(np.unique(m["glb"][m["dirichlet"] == 1])) == c["dirichlet_unique"]
+        off, idx, gid = gs.groups()
+        assert np.all(np.diff(gid) > 0)
+        del m, gs, mult
+
+
+def test_shared_nodes_coincide_and_walls():
+    m = oracle.box_mesh(3, 3, 3, 6, 0.05)
+    gs = oracle.GS(m["glb"])
+    off, idx, gid = gs.groups()
+    for c in ("x", "y", "z"):
+        a = m[c]
+        for g in range(len(gid)):
+            v = a[idx[off[g]:off[g + 1]]]
+            assert np.all(v == v[0])
+        # indices inside a group ascend
+    assert all(np.all(np.diff(idx[off[g]:off[g + 1]]) > 0) for g in range(len(gid)))
+    m0 = oracle.box_mesh(3, 3, 3, 6, 0.0)
+    on_wall = np.zeros(len(m0["x"]), bool)
+    for c in ("x", "y", "z"):
+        on_wall |= (m0[c] == 0.0) | (m0[c] == 1.0)
+    np.testing.assert_array_equal(on_wall, m0["dirichlet"].astype(bool))
+
+
+def test_mesh_matches_brute():
+    xyz, gid, dr = brute.box(2, 5, 0.05)
+    m = oracle.box_mesh(2, 2, 2, 5, 0.05)
+    np.testing.assert_array_equal(m["glb"], gid.reshape(-1))
+    np.testing.assert_array_equal(m["dirichlet"].astype(bool), dr.reshape(-1))
+    for c, name in enumerate("xyz"):
+        np.testing.assert_allclose(m[name], xyz[:, :, c].reshape(-1), rtol=0, atol=1e-15)
+
+
+# ------------------------------------------------------------------ geometry (Eq. 9 G^e)
+@pytest.mark.parametrize("nx,lx", [(2, 4), (3, 6), (2, 8)])
+def test_affine_geometry_closed_form(nx, lx):
+    P = oracle.Problem(nx, lx, 0.0)
+    h = 1.0 / nx
+    rho = np.tile(np.kron(P.w, np.kron(P.w, P.w)), P.nelv)
+    for f in range(3):
+        np.testing.assert_allclose(P.G[f], rho * h / 2, rtol=1e-13)
+    assert np.abs(P.G[3:]).max() < 1e-15
+    np.testing.assert_allclose(P.B, rho * (h / 2) ** 3, rtol=1e-12)
+
+
+@pytest.mark.parametrize("nx,lx,eps", [(2, 4, 0.0), (4, 6, 0.0), (2, 4, 0.05), (4, 6, 0.05), (2, 8, 0.05)])
+def test_volume_is_one(nx, lx, eps):
+    """The sine map has det = 1 + eps^2 (...) + eps^3 (...) whose correction terms
+    all integrate to zero over the unit cube; GLL quadrature of the
+    isoparametric map reproduces the volume 1."""
+    P = oracle.Problem(nx, lx, eps)
+    assert abs(P.B.sum() - 1.0) < (1e-14 if eps == 0 else 1e-10)
+
+
+@pytest.mark.parametrize("nx,lx", [(2, 4), (3, 6), (2, 8)])
+def test_coordinate_energy_identity_curved(nx, lx):
+    """For u = x (the isoparametric coordinate, exact in the space):
+    grad u = e_x at every quadrature point, so u^T A_L u = sum B and
+    y^T A_L x = 0.  Pins the inverse metric and the G index order."""
+    P = oracle.Problem(nx, lx, 0.05)
+    X = {"x": P.x, "y": P.y, "z": P.z}
+    vol = P.B.sum()
+    for a in "xyz":
+        Au = P.ax_local(X[a])
+        for b in "xyz":
+            val = np.dot(X[b], Au)
+            if a == b:
+                assert abs(val - vol) < 1e-12
+            else:
+                assert abs(val) < 1e-12
+
+
+def test_geometry_vs_brute_element():
+    P = oracle.Problem(2, 5, 0.05)
+    xyz, _, _ = brute.box(2, 5, 0.05)
+    for e in range(P.nelv):
+        _, detJ, Bb = brute.element_matrix(xyz[e], 5)
+        s = slice(e * 125, (e + 1) * 125)
+        np.testing.assert_allclose(P.J[s], detJ, rtol=1e-12)
+        np.testing.assert_allclose(P.B[s], Bb, rtol=1e-12)
+
+
+# ------------------------------------------------------------------ ax_helm (Eq. 9)
+@pytest.mark.parametrize("lx", [3, 6, 8, 12])
+def test_constants_in_nullspace(lx):
+    P = oracle.Problem(2, lx, 0.05)
+    w = P.ax_local(np.ones(P.n))
+    assert np.abs(w).max() < 1e-13 * np.abs(P.G).max() * lx ** 2
+
+
+def test_symmetric_and_variable_coefficients():
+    P = oracle.Problem(3, 6, 0.05)
+    u = workloads.uniform(P.n, 0)
+    v = workloads.uniform(P.n, 1)
+    h1 = 1.0 + 0.5 * workloads.uniform(P.n, 2)
+    h2 = 2.0 + workloads.uniform(P.n, 3)
+    P.set_coef(h1, h2)
+    a = np.dot(v, P.ax_local(u))
+    b = np.dot(u, P.ax_local(v))
+    assert abs(a - b) <= 1e-13 * abs(a)
+
+
+def test_assembled_psd_with_constant_nullspace():
+    P = oracle.Problem(2, 4, 0.05)
+    ids, rep = np.unique(P.glb, return_index=True)
+    ng = len(ids)
+    pos = np.searchsorted(ids, P.glb)
+    A = np.zeros((ng, ng))
+    for j in range(ng):
+        u = (pos == j).astype(np.float64)
+        w = P.gs.op(P.ax_local(u))
+        A[:, j] = w[rep]
+    assert np.abs(A - A.T).max() < 1e-13 * np.abs(A).max()
+    ev = np.linalg.eigvalsh(A)
+    assert ev[0] > -1e-13 * ev[-1]
+    assert ev[1] > 1e-6 * ev[-1]            # exactly one zero mode: the constants
+    assert abs(ev[0]) < 1e-12 * ev[-1]
+
+
+def _poly_energy(a, b, c):
+    """int_[0,1]^3 |grad x^a y^b z^c|^2."""
+    def m(p):  # int_0^1 t^p
+        return 1.0 / (p + 1)
+    t = 0.0
+    if a: t += a * a * m(2 * a - 2) * m(2 * b) * m(2 * c)
+    if b: t += b * b * m(2 * a) * m(2 * b - 2) * m(2 * c)
+    if c: t += c * c * m(2 * a) * m(2 * b) * m(2 * c - 2)
+    return t
+
+
+@pytest.mark.parametrize("lx", [4, 5, 8])
+def test_energy_exact_on_affine(lx):
+    """u^T A_L u = int |grad u|^2 exactly for u in Q_{N-1} on affine elements
+    (GLL quadrature exact for degree 2N-1); fails for degree (N,1,0)."""
+    N = lx - 1
+    P = oracle.Problem(2, lx, 0.0)
+    for (a, b, c) in [(N - 1, N - 1, N - 1), (1, 0, 0), (N - 1, 1, 0), (0, N - 1, 2), (N, 0, 0)]:
+        u = P.x ** a * P.y ** b * P.z ** c
+        e = np.dot(u, P.ax_local(u))
+        assert abs(e - _poly_energy(a, b, c)) < 1e-12 * max(1.0, _poly_energy(a, b, c)), (a, b, c)
+    if N <= 4:  # the degree-2N quadrature error is visible well above rounding
+        u = P.x ** N * P.y
+        e = np.dot(u, P.ax_local(u))
+        assert abs(e - _poly_energy(N, 1, 0)) > 1e-8
+
+
+def test_linear_function_interior_rows_vanish_affine():
+    P = oracle.Problem(3, 6, 0.0)
+    u = 2 * P.x - 3 * P.y + P.z + 0.5
+    w = P.gs.op(P.ax_local(u))
+    interior = P.dirichlet == 0
+    assert np.abs(w[interior]).max() < 1e-13
+
+
+@pytest.mark.parametrize("nx,lx", [(1, 6), (2, 3), (2, 4)])
+def test_operator_vs_dense_brute_force(nx, lx):
+    """Oracle's assembled, masked operator equals the numpy chain-rule stiffness
+    matrix (curved mesh, variable h1 and h2), on the free unique nodes."""
+    eps = 0.05
+    P = oracle.Problem(nx, lx, eps)
+    h1 = np.exp(0.3 * workloads.uniform(P.n, 5))
+    h2 = 3.0 + workloads.uniform(P.n, 6)
+    P.set_coef(h1, h2)
+    A, pos, gid, _ = brute.assembled(nx, lx, eps, h1.reshape(P.nelv, -1), h2.reshape(P.nelv, -1))
+    nf = A.shape[0]
+    p_loc = pos[P.glb]
+    Ao = np.zeros_like(A)
+    rep = np.array([np.flatnonzero(p_loc == j)[0] for j in range(nf)])
+    for j in range(nf):
+        u = (p_loc == j).astype(np.float64)
+        Ao[:, j] = P.apply(u)[rep]
+    assert np.abs(Ao - A).max() <= 1e-12 * np.abs(A).max()
+
+
+# ------------------------------------------------------------------ gather-scatter (Eq. 10)
+def test_gs_identities():
+    P = oracle.Problem(3, 5, 0.05)
+    u = workloads.uniform(P.n, 7)
+    g = P.gs.op(u)
+    assert abs(np.sum(g / P.mult) - np.sum(u)) < 1e-11
+    np.testing.assert_allclose(P.gs.op(g / P.mult), g, rtol=1e-14, atol=1e-14)
+    np.testing.assert_array_equal(P.gs.op(np.ones(P.n)), P.mult)
+
+
+def test_gs_equals_boolean_QQT():
+    P = oracle.Problem(2, 4, 0.05)
+    ids = np.unique(P.glb)
+    Q = (P.glb[:, None] == ids[None, :]).astype(np.float64)   # scatter Q, n_L x n_g
+    u = np.floor(workloads.uniform(P.n, 8) * 1000.0)          # integers: sums are exact
+    np.testing.assert_array_equal(P.gs.op(u), Q @ (Q.T @ u))
+
+
+# ------------------------------------------------------------------ Jacobi (Section 4)
+def test_jacobi_diagonal_vs_dense():
+    nx, lx, eps = 2, 4, 0.05
+    P = oracle.Problem(nx, lx, eps)
+    h1 = np.exp(0.3 * workloads.uniform(P.n, 5))
+    h2 = 3.0 + workloads.uniform(P.n, 6)
+    P.set_coef(h1, h2)
+    A, pos, _, _ = brute.assembled(nx, lx, eps, h1.reshape(P.nelv, -1), h2.reshape(P.nelv, -1))
+    p_loc = pos[P.glb]
+    d = P.gs.op(P.diag_local())
+    free = p_loc >= 0
+    np.testing.assert_allclose(d[free], np.diag(A)[p_loc[free]], rtol=1e-13)
+    np.testing.assert_allclose(P.dinv[free], 1.0 / np.diag(A)[p_loc[free]], rtol=1e-13)
+    assert np.all(P.dinv[~free] == 0.0)
+
+
+# ------------------------------------------------------------------ PCG (Section 4)
+def test_pcg_config1_matches_dense_solve():
+    """64 affine elements, lx=6: 50 Jacobi-PCG steps on the manufactured sine
+    load reproduce the dense solve, and the discrete solution is within the
+    spectral discretisation error of u* = sin sin sin."""
+    wl = workloads.WORKLOADS["poisson_4x4x4_lx6"]
+    P = oracle.Problem(wl.nx, wl.lx, wl.eps)
+    f = workloads.sine_source(P.x, P.y, P.z)
+    b = P.assemble_rhs(P.B * f)
+    x, info = P.pcg(b, rtol=0.0, max_iter=wl.iters)
+    assert info["iters"] == 50 and info["rel_res"] < 1e-14
+    A, pos, _, _ = brute.assembled(wl.nx, wl.lx, wl.eps)
+    p_loc = pos[P.glb]
+    free = p_loc >= 0
+    rep = np.array([np.flatnonzero(p_loc == j)[0] for j in range(A.shape[0])])
+    xd = np.linalg.solve(A, b[rep])
+    np.testing.assert_allclose(x[free], xd[p_loc[free]], rtol=0, atol=1e-12 * np.abs(xd).max())
+    assert np.abs(x - workloads.sine_exact(P.x, P.y, P.z)).max() < 1e-7
+
+
+def test_spectral_convergence():
+    """Manufactured Poisson solution on 2^3 affine elements: the max nodal error
+    falls geometrically with N (Eq. 7-9 discretisation of Eq. 4-6)."""
+    errs = []
+    for lx in range(3, 10):
+        P = oracle.Problem(2, lx, 0.0)
+        b = P.assemble_rhs(P.B * workloads.sine_source(P.x, P.y, P.z))
+        x, info = P.pcg(b, rtol=1e-14)
+        assert info["status"] == 0
+        errs.append(np.abs(x - workloads.sine_exact(P.x, P.y, P.z)).max())
+    errs = np.array(errs)
+    assert np.all(errs[1:] < 0.25 * errs[:-1]), errs
+    assert errs[-1] < 1e-7
+
+
+def test_pcg_roundtrip_curved_variable():
+    P = oracle.Problem(3, 6, 0.05, h1=1.0, h2=10.0)
+    u = _cont(P, 9, zero_dirichlet=True)
+    b = P.apply(u)
+    x, info = P.pcg(b, rtol=1e-13)
+    assert info["status"] == 0
+    assert np.abs(x - u).max() < 1e-9
+    assert P.true_rel_res(x, b) < 2e-13
+
+
+def test_pcg_status_codes():
+    P = oracle.Problem(2, 5, 0.05)
+    b = P.assemble_rhs(workloads.uniform(P.n, 1))
+    _, info = P.pcg(b, rtol=1e-12, max_iter=3)
+    assert info["status"] == 1 and info["iters"] == 3
+    x, info = P.pcg(np.zeros(P.n), rtol=1e-10)
+    assert info["status"] == 0 and info["iters"] == 0 and not x.any()
+
+
+# ------------------------------------------------------------------ adjoint / gradient
+def test_adjoint_euler_identity():
+    """sum_p h1_p g_p(v, u) = v^T A_L(h1) u for h2 = 0 (Eq. 9 is linear in h1)."""
+    P = oracle.Problem(3, 8, 0.05)
+    h1 = np.exp(0.5 * workloads.uniform(P.n, 4))
+    P.set_coef(h1, 0.0)
+    u = workloads.uniform(P.n, 0)
+    v = workloads.uniform(P.n, 1)
+    g = P.adjoint(u, v)
+    lhs = np.dot(h1, g)
+    rhs = np.dot(v, P.ax_local(u))
+    assert abs(lhs - rhs) <= 1e-13 * abs(rhs)
+    # the adjoint is symmetric in (u, v) and g(u, u) >= 0 pointwise (G is SPD)
+    np.testing.assert_allclose(P.adjoint(v, u), g, rtol=1e-12, atol=1e-15)
+    assert P.adjoint(u, u).min() >= -1e-15
+
+
+def test_adjoint_central_difference():
+    P = oracle.Problem(2, 6, 0.05)
+    h1 = np.exp(0.5 * workloads.uniform(P.n, 4))
+    u = workloads.uniform(P.n, 0)
+    v = workloads.uniform(P.n, 1)
+    dh = workloads.uniform(P.n, 2)
+    g = P.adjoint(u, v)
+    eps = 1e-6
+    f = lambda h: np.dot(v, oracle.ax_helm(P.lx, P.D, P.G, P.B, u, h, 0.0))
+    fd = (f(h1 + eps * dh) - f(h1 - eps * dh)) / (2 * eps)
+    assert abs(fd - np.dot(dh, g)) <= 1e-8 * abs(fd)
+
+
+def _oracle_loss_grad(P, h1, h2, b, ut, rtol=1e-14):
+    P.set_coef(h1, h2)
+    u, i1 = P.pcg(b, rtol=rtol)
+    assert i1["status"] == 0
+    d = u - ut
+    L = 0.5 * P.dot(d, d)
+    rhs = np.where(P.dirichlet.astype(bool), 0.0, d)
+    lam, i2 = P.pcg(rhs, rtol=rtol)
+    assert i2["status"] == 0
+    return L, -P.adjoint(u, lam)
+
+
+def test_gradient_vs_dense_finite_differences():
+    """dL/dh1 from the oracle's forward + adjoint solves and the h1-adjoint
+    contraction equals central differences of a dense brute-force solve."""
+    nx, lx, eps, h2 = 2, 3, 0.05, 10.0
+    P = oracle.Problem(nx, lx, eps)
+    field = workloads.grf(workloads.SEED_GRF)
+    h1 = np.exp(field(P.x, P.y, P.z))
+    b = P.assemble_rhs(P.B * workloads.sine_source(P.x, P.y, P.z))
+    ut = _cont(P, 12, zero_dirichlet=True) * 0.1
+    L, grad = _oracle_loss_grad(P, h1, h2, b, ut)
+
+    A0, pos, _, _ = brute.assembled(nx, lx, eps, h1.reshape(P.nelv, -1), h2)
+    p_loc = pos[P.glb]
+    nf = A0.shape[0]
+    rep = np.array([np.flatnonzero(p_loc == j)[0] for j in range(nf)])
+
+    def loss(h):
+        A, _, _, _ = brute.assembled(nx, lx, eps, h.reshape(P.nelv, -1), h2)
+        u = np.linalg.solve(A, b[rep])
+        return 0.5 * np.sum((u - ut[rep]) ** 2)
+
+    assert abs(loss(h1) - L) <= 1e-10 * abs(L)
+    rng = np.random.default_rng(0)
+    for p in rng.choice(P.n, 12, replace=False):
+        e = np.zeros(P.n)
+        e[p] = 1e-6 * h1[p]
+        fd = (loss(h1 + e) - loss(h1 - e)) / (2e-6 * h1[p])
+        assert abs(fd - grad[p]) <= 1e-6 * np.abs(grad).max(), (p, fd, grad[p])
