@@ -1,0 +1,196 @@
+"""Benchmark of the SEM Helmholtz hot path on one MI355X.
+
+Workload: 32^3 = 32768 curved hexahedra on [0,1]^3, lx = 8 (N = 7), 16,777,216 local
+points, Poisson (h1 = 1, h2 = 0), homogeneous Dirichlet walls.  Synthetic inputs:
+operand u ~ U[-1,1] (seed 0), load vector U[-1,1] (seed 1) assembled and masked.
+
+One step = the whole hot path once:
+  (a) R back-to-back ax_helm launches (the paper's matrix-vector benchmark loop,
+      Listing 2) on u, followed by one gs_op,
+  (b) an FP64 Jacobi-PCG solve to relative residual 1e-10,
+  (c) the mixed solve (FP64 flexible CG around FP32 Jacobi-PCG) to 1e-10.
+value = FP64 ax_helm GDOF/s = n_p / (average ax_helm launch time), from HIP events
+on the launch stream over the timed steps.  The JSON line also carries both solve
+times, iteration counts, the roofline of the ax_helm kernel and the CPU oracle
+baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Ax GDOF/s + PCG solve time to 1e-10, lx=8 32³ elems, FP64 vs FP32-mixed"
+HBM_PEAK_GBS = 8000.0
+AX_WORDS_PER_POINT = 8      # u, w and the six geometric factors (h1 = 1, h2 = 0)
+CG_WORDS_PER_POINT = 11     # matvec: r, dinv, p_old, 6 G in; p, w out
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, seconds=15.0):
+    """The oracle's ax_helm on the same 32^3, lx=8 curved mesh, timed on the host."""
+    import oracle
+    import workloads
+
+    t0 = time.time()
+    m = oracle.box_mesh(wl.nx, wl.nx, wl.nx, wl.lx, wl.eps)
+    xi, w = oracle.gll(wl.lx)
+    D = oracle.deriv_matrix(xi)
+    G, B, _ = oracle.geometry(wl.lx, D, w, m["x"], m["y"], m["z"])
+    del m
+    u = workloads.uniform(wl.n_local, workloads.SEED_U)
+    log(f"cpu baseline setup {time.time() - t0:.1f}s")
+    reps, t = 0, 0.0
+    while t < seconds or reps < 2:
+        t1 = time.perf_counter()
+        oracle.ax_helm(wl.lx, D, G, B, u, 1.0, 0.0)
+        t += time.perf_counter() - t1
+        reps += 1
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = min(cores, os.cpu_count() or cores)
+    return {"value": wl.n_local * reps / t / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
+            "sample": f"{reps} oracle ax_helm applications on the full 32^3 lx=8 curved mesh "
+                      f"({wl.n_local} local points), FP64, {t:.1f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--reps", type=int, default=20, help="ax_helm launches per step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the multi-GPU path "
+              "is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+    from paper_2107_01243_amd import sem
+
+    wl = workloads.WORKLOADS["poisson_32x32x32_lx8"]
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    P = sem.BoxProblem.build(wl.nx, wl.lx, wl.eps, fp32=True)
+    u = torch.from_numpy(workloads.uniform(P.n, workloads.SEED_U)).cuda()
+    b = P.assemble(torch.from_numpy(workloads.uniform(P.n, workloads.SEED_RHS)).cuda())
+    w = torch.empty_like(u)
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    log(f"setup {time.time() - t0:.1f}s, n_local={P.n}")
+
+    stream = torch.cuda.current_stream()
+
+    def step(record):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        for _ in range(a.reps):
+            sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
+        ev[1].record(stream)
+        P.gs.op(w)
+        ev[2].record(stream)
+        t1 = time.perf_counter()
+        x.zero_()
+        info64 = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, check_every=50)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        infom, tm = None, None
+        if not a.no_mixed:
+            t1 = time.perf_counter()
+            x.zero_()
+            infom = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, mixed=True,
+                                  inner_rtol=1e-4, inner_max_iter=5000, check_every=50)
+            torch.cuda.synchronize()
+            tm = time.perf_counter() - t1
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        if record is not None:
+            record["ax_ms"].append(ev[0].elapsed_time(ev[1]))
+            record["gs_ms"].append(ev[1].elapsed_time(ev[2]))
+            record["pcg64_s"].append(t64)
+            record["it64"].append(info64[0]["iters"])
+            record["tr64"].append(info64[0]["true_rel_res"])
+            if infom is not None:
+                record["mixed_s"].append(tm)
+                record["outer"].append(infom[0]["iters"])
+                record["inner"].append(infom[0]["inner_iters"])
+                record["trm"].append(infom[0]["true_rel_res"])
+        return info64, infom
+
+    for i in range(a.warmup):
+        step(None)
+        log(f"warmup {i + 1}/{a.warmup} done")
+    rec = {k: [] for k in ("ax_ms", "gs_ms", "pcg64_s", "it64", "tr64", "mixed_s", "outer", "inner", "trm")}
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for i in range(a.steps):
+        step(rec)
+        log(f"step {i + 1}/{a.steps}: ax {rec['ax_ms'][-1] / a.reps * 1e3:.1f} us/launch, "
+            f"pcg64 {rec['pcg64_s'][-1]:.3f}s ({rec['it64'][-1]} it)"
+            + (f", mixed {rec['mixed_s'][-1]:.3f}s ({rec['outer'][-1]} outer / {rec['inner'][-1]} inner)"
+               if rec["mixed_s"] else ""))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - tb
+
+    ax_s = sum(rec["ax_ms"]) / 1e3 / (a.reps * a.steps)
+    gdofs = P.n / ax_s / 1e9
+    achieved = AX_WORDS_PER_POINT * 8 * P.n / ax_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(gdofs, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(total / a.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "elements": wl.nelv, "lx": wl.lx, "n_local": P.n,
+                   "n_unique": wl.n_unique, "deformation": wl.eps, "h1": 1.0, "h2": 0.0,
+                   "rtol": wl.rtol, "ax_launches_per_step": a.reps},
+        "ax_us": round(ax_s * 1e6, 2),
+        "gs_us": round(float(np.mean(rec["gs_ms"])) * 1e3, 2),
+        "pcg_fp64_solve_s": round(float(np.median(rec["pcg64_s"])), 4),
+        "pcg_fp64_iters": int(np.median(rec["it64"])),
+        "pcg_fp64_true_rel_res": float(np.max(rec["tr64"])),
+        "pcg_fp64_ms_per_iter": round(float(np.median(rec["pcg64_s"])) / max(1, int(np.median(rec["it64"]))) * 1e3, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_ax_helm<8, double, 1>", "bytes_per_point": AX_WORDS_PER_POINT * 8},
+    }
+    if rec["mixed_s"]:
+        out.update({
+            "pcg_mixed_solve_s": round(float(np.median(rec["mixed_s"])), 4),
+            "pcg_mixed_outer_iters": int(np.median(rec["outer"])),
+            "pcg_mixed_inner_iters": int(np.median(rec["inner"])),
+            "pcg_mixed_true_rel_res": float(np.max(rec["trm"])),
+            "mixed_speedup_vs_fp64": round(float(np.median(rec["pcg64_s"])) / float(np.median(rec["mixed_s"])), 3),
+        })
+    if not a.no_cpu_baseline:
+        del P, u, w, x, b
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

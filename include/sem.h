@@ -1,0 +1,208 @@
+/*
+ * sem.h -- C ABI of libsem, the MI355X (gfx950) spectral-element Helmholtz hot path.
+ *
+ * The operations follow Jansson et al., "Neko: a modern, portable, and
+ * scalable framework for high-fidelity computational fluid dynamics"
+ * (arXiv 2107.01243):
+ *   - sem_ax_helm          the matrix-free element operator of Section 2, Eq. 9-10,
+ *                          with the argument order of the ax_compute interface
+ *                          (Section 3.1, Listing 1: w, u, coef, msh, Xh);
+ *   - sem_gs_op            the gather-scatter QQ^T of Eq. 10 (Section 3.2,
+ *                          Algorithm 1, its local gather + scatter);
+ *   - sem_pcg_solve        the Jacobi-preconditioned CG of the velocity solve
+ *                          (Section 4), in FP64 or as FP64 flexible CG around an
+ *                          FP32 inner solve ("other precision formats", Section 10);
+ *   - sem_ax_helm_adjoint  d(v^T A_L(h1) u)/d h1 per quadrature point, from the
+ *                          linearity of Eq. 9 in the coefficient.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout.  A "local" field holds n_p = nelv * lx^3 values, element-major, point
+ *   (i,j,k) of element e at e*lx^3 + i + lx*(j + lx*k) (i fastest): the 4-D arrays
+ *   of Listing 1.  nfields > 1 fields are stored back to back (field f starts at
+ *   f * n_p).  Geometric factors are 6 planes of n_p values: G11, G22, G33, G12,
+ *   G13, G23.
+ * Memory.  Pointers documented "device" are caller-owned GPU allocations; "host"
+ *   pointers are caller-owned CPU memory.  Handles and every internal buffer are
+ *   owned by the library and released by the matching *_destroy call.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   sem_ax_helm, sem_gs_op, sem_mask and sem_ax_helm_adjoint only enqueue work
+ *   and return.  sem_pcg_solve synchronises the stream to poll convergence.
+ * Errors.  Every call returns a sem_status; nothing aborts or throws.  Invalid
+ *   arguments are rejected before any launch.  sem_last_error() returns a
+ *   thread-local description of the last failure.
+ * Device.  Handles are bound to the HIP device current at creation; calls must
+ *   be made with that device current.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SEM_OK = 0,
+    SEM_ERR_INVALID = -1,        /* bad argument (size, lx, NULL, aliasing, dtype)   */
+    SEM_ERR_OOM = -2,            /* device or host allocation failed                  */
+    SEM_ERR_HIP = -3,            /* a HIP runtime call failed (message has details)   */
+    SEM_ERR_NOT_CONVERGED = -4,  /* solver hit max_iter; x and info are valid         */
+    SEM_ERR_BREAKDOWN = -5,      /* non-positive or non-finite curvature in CG        */
+    SEM_ERR_UNSUPPORTED = -6     /* valid request this build does not implement      */
+} sem_status;
+
+typedef enum { SEM_F64 = 0, SEM_F32 = 1 } sem_dtype;
+
+/* Library limits: lx in [SEM_LX_MIN, SEM_LX_MAX]; nfields in {1, 3}. */
+#define SEM_LX_MIN 2
+#define SEM_LX_MAX 16
+
+typedef struct sem_space_s *sem_space; /* Xh: lx, GLL points/weights, D (Eq. 7-9)   */
+typedef struct sem_mesh_s *sem_mesh;   /* msh: nelv, lx, global ids, Dirichlet mask  */
+typedef struct sem_coef_s *sem_coef;   /* coef: G, B, h1, h2, Jacobi cache            */
+typedef struct sem_gs_s *sem_gs;       /* gs: pair list + block lists for QQ^T        */
+
+/* Flag for sem_coef_create*: also keep FP32 copies of G, B, D (needed by SEM_F32
+ * calls and by the mixed-precision solve). */
+#define SEM_COEF_F32 1u
+
+/* ---------------------------------------------------------------- space (Xh)
+ * GLL points xi (end points -1, +1, interior the roots of L'_N), weights
+ * w_i = 2/(N(N+1) L_N(xi_i)^2) and the derivative matrix D[i*lx + l] = l_l'(xi_i)
+ * of the degree-N Lagrange basis through them (Section 2, Eq. 7-9; Eq. 7 is
+ * printed garbled in the paper and is read as that basis).
+ * lx outside [SEM_LX_MIN, SEM_LX_MAX] -> SEM_ERR_INVALID. */
+sem_status sem_space_create(int lx, sem_space *Xh);
+/* Host copies: xi[lx], w[lx], D[lx*lx] (any may be NULL). */
+sem_status sem_space_get(sem_space Xh, double *xi, double *w, double *D);
+void sem_space_destroy(sem_space Xh);
+
+/* ---------------------------------------------------------------- synthetic box mesh
+ * Host helper producing the structured test meshes: nx*ny*nz hexahedra on
+ * [0,1]^3, element e = ex + nx*(ey + ny*ez), node (i,j,k) at
+ * ((ex + (xi_i+1)/2)/nx, (ey + (xi_j+1)/2)/ny, (ez + (xi_k+1)/2)/nz), then moved by
+ * x += eps sin(2 pi y) sin(2 pi z), y += eps sin(2 pi z) sin(2 pi x),
+ * z += eps sin(2 pi x) sin(2 pi y) (all evaluated at the undeformed point).
+ * Global id = (ex*N+i) + Mx*((ey*N+j) + My*(ez*N+k)), M = n*N + 1 per direction.
+ * dirichlet = 1 on the six walls (Eq. 5).  Outputs are host arrays of n_p
+ * values (xyz: 3*n_p, x plane then y then z); any output may be NULL.
+ * Note: the library takes its own GLL points from lx, so a mesh is tied to lx. */
+sem_status sem_box_mesh(int nx, int ny, int nz, int lx, double eps,
+                        int64_t *glb, uint8_t *dirichlet, double *xyz);
+
+/* ---------------------------------------------------------------- mesh (msh)
+ * glb_host: n_p = nelv*lx^3 global ids (any non-negative int64, "a unique global
+ * number" per degree of freedom, Section 2).  dirichlet_host: n_p flags (nonzero =
+ * homogeneous Dirichlet node, Eq. 5) or NULL for none.  Copies are taken.
+ * The Dirichlet flags must agree on all copies of a global id (else INVALID). */
+sem_status sem_mesh_create(int64_t nelv, int lx, const int64_t *glb_host,
+                           const uint8_t *dirichlet_host, sem_mesh *msh);
+sem_status sem_mesh_size(sem_mesh msh, int64_t *nelv, int *lx, int64_t *n_local,
+                         int64_t *n_unique, int64_t *n_dirichlet_local);
+void sem_mesh_destroy(sem_mesh msh);
+
+/* ---------------------------------------------------------------- gather-scatter (gs)
+ * Builds the QQ^T maps of Eq. 10 from the mesh's global ids (Section 3.2): local
+ * indices are grouped by global id; ids with exactly two copies form the pair
+ * list (the "injective" ids of Section 3.2), ids with more copies form variable
+ * length blocks; ids with one copy are skipped.  Canonical order: pairs and
+ * blocks by ascending global id, indices within a group ascending.  The sum
+ * over a group is taken in that order, so sem_gs_op is bit-reproducible.
+ * Indices are int32: n_p must be < 2^31. */
+sem_status sem_gs_create(sem_mesh msh, sem_gs *gs);
+sem_status sem_gs_sizes(sem_gs gs, int64_t *npairs, int64_t *nblocks, int64_t *nblock_entries);
+/* Host copies of the maps: pairs[2*npairs] (a0,b0,a1,b1,...), blk_ptr[nblocks+1],
+ * blk_idx[nblock_entries]; mult[n_p] (multiplicity of each local point, uint8,
+ * may be NULL).  Any output may be NULL. */
+sem_status sem_gs_export_maps(sem_gs gs, int32_t *pairs, int64_t *blk_ptr, int32_t *blk_idx,
+                              uint8_t *mult);
+void sem_gs_destroy(sem_gs gs);
+
+/* u <- QQ^T u on nfields contiguous local fields (device, dtype dt), in place
+ * (Eq. 10; Algorithm 1, local gather + scatter). */
+sem_status sem_gs_op(void *u, int nfields, sem_gs gs, sem_dtype dt, void *stream);
+
+/* u <- 0 on the mesh's Dirichlet points (Eq. 5), nfields contiguous fields. */
+sem_status sem_mask(void *u, int nfields, sem_mesh msh, sem_dtype dt, void *stream);
+
+/* ---------------------------------------------------------------- coefficients (coef)
+ * Geometric factors of Eq. 9 from nodal coordinates xyz_dev (device FP64, 3*n_p:
+ * x plane, y plane, z plane), isoparametric: metric = D applied to the
+ * coordinates, J its determinant, G_ab = rho J grad r_a . grad r_b, B = rho J,
+ * rho the tensor GLL weight.  Fails with SEM_ERR_INVALID if any J <= 0.
+ * h1 = 1, h2 = 0 until sem_coef_set_helmholtz is called.  Enqueued on stream and
+ * synchronised before return. */
+sem_status sem_coef_create(sem_space Xh, sem_mesh msh, const double *xyz_dev, unsigned flags,
+                           void *stream, sem_coef *coef);
+/* Same, from given factors: G6_dev (device FP64, 6*n_p), B_dev (device FP64, n_p). */
+sem_status sem_coef_create_from_G(sem_space Xh, sem_mesh msh, const double *G6_dev,
+                                  const double *B_dev, unsigned flags, void *stream,
+                                  sem_coef *coef);
+/* Helmholtz coefficients A = h1 K + h2 B (Section 4: h1 = 1/Re, h2 = b0/dt).
+ * h1_dev / h2_dev: device FP64 fields of n_p values (copied), or NULL to use the
+ * scalar.  Invalidates the cached Jacobi diagonal. */
+sem_status sem_coef_set_helmholtz(sem_coef coef, const double *h1_dev, double h1,
+                                  const double *h2_dev, double h2, void *stream);
+/* Device copies of the FP64 factors (G6_dev: 6*n_p, B_dev: n_p; either may be NULL). */
+sem_status sem_coef_export(sem_coef coef, double *G6_dev, double *B_dev, void *stream);
+void sem_coef_destroy(sem_coef coef);
+
+/* ---------------------------------------------------------------- operators
+ * w = A_L u on nfields (1 or 3) contiguous fields: per element
+ * w = h1 D^T G D u + h2 B u (Eq. 9, unassembled; Eq. 10 is completed by
+ * sem_gs_op).  u, w: device, dtype dt, nfields*n_p values, must not overlap.
+ * dt = SEM_F32 needs a coef created with SEM_COEF_F32 (FP32 G, B, D, h1, h2). */
+sem_status sem_ax_helm(void *w, const void *u, sem_coef coef, sem_mesh msh, sem_space Xh,
+                       int nfields, sem_dtype dt, void *stream);
+
+/* g_p = (D v)_p^T G_p (D u)_p at every local point = d(v^T A_L(h1) u)/d h1_p.
+ * g, u, v: device, dtype dt, n_p values; g must not overlap u or v. */
+sem_status sem_ax_helm_adjoint(void *g, const void *u, const void *v, sem_coef coef,
+                               sem_mesh msh, sem_space Xh, sem_dtype dt, void *stream);
+
+/* Jacobi inverse used by the solver: dinv = 1 / QQ^T(diag A_L), 0 on Dirichlet
+ * points (device FP64 output, n_p). */
+sem_status sem_jacobi_inverse(double *dinv, sem_coef coef, sem_mesh msh, sem_space Xh,
+                              sem_gs gs, void *stream);
+
+/* ---------------------------------------------------------------- solver */
+typedef struct {
+    double rtol;        /* stop when |r|/|b| <= rtol (unique-node 2-norms of the
+                           recursive residual); <= 0: run exactly max_iter iterations */
+    int max_iter;       /* outer iteration cap (>= 1)                                 */
+    int check_every;    /* host polls convergence every this many iterations (>= 1)   */
+    int mixed;          /* 0: FP64 Jacobi-PCG; 1: FP64 flexible CG preconditioned by
+                           an FP32 Jacobi-PCG inner solve (needs SEM_COEF_F32)         */
+    double inner_rtol;  /* mixed: relative tolerance of each inner solve               */
+    int inner_max_iter; /* mixed: iteration cap of each inner solve                    */
+    int use_x0;         /* 1: x holds the initial guess on entry; 0: start from 0      */
+} sem_pcg_params;
+
+typedef struct {
+    int iters;          /* outer iterations performed                                  */
+    int inner_iters;    /* mixed: total inner FP32 iterations                          */
+    int converged;      /* 1 when rel_res <= rtol                                      */
+    double rel_res;     /* recursive |r|/|b| at exit                                   */
+    double true_rel_res;/* |b - A x|/|b| recomputed in FP64 at exit                    */
+} sem_pcg_info;
+
+/* Solve mask QQ^T A_L(h1,h2) x = b for nfields (1 or 3) independent fields.
+ * b: device FP64, assembled and masked (b = mask QQ^T f), nfields*n_p values.
+ * x: device FP64, in: guess (if use_x0), out: solution.  info: host array of
+ * nfields entries (may be NULL).  Returns SEM_ERR_NOT_CONVERGED or
+ * SEM_ERR_BREAKDOWN with x and info valid when a field fails. */
+sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef, sem_mesh msh,
+                         sem_space Xh, sem_gs gs, const sem_pcg_params *params,
+                         sem_pcg_info *info, void *stream);
+
+/* ---------------------------------------------------------------- misc */
+const char *sem_last_error(void);
+const char *sem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEM_H */

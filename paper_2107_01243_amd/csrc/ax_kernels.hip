@@ -1,0 +1,582 @@
+// ax_kernels.hip -- element-local kernels of the SEM Helmholtz operator for gfx950.
+//
+// Operator (Jansson et al., arXiv 2107.01243, Section 2, Eq. 9):
+//   w_e = h1 D^T G_e D u_e + h2 B_e u_e  on every hexahedral element,
+// with D the 1-D GLL derivative matrix applied along r, s and t, and G_e the six
+// geometric factors (G11, G22, G33, G12, G13, G23) per point.
+//
+// Work decomposition ("pencil" layout).  One element is handled by lx*lx lanes.
+// A lane with in-element index t = a + lx*b owns, at different stages,
+//   r-pencil: the lx points (i = 0..lx-1, j = a, k = b)   (contiguous in HBM)
+//   s-pencil: the lx points (i = a, j = 0..lx-1, k = b)
+//   t-pencil: the lx points (i = a, j = b, k = 0..lx-1)
+// Each 1-D derivative is then a register-only lx x lx matrix-vector product whose
+// D entries are wave-uniform (D travels in the kernel-argument segment and is read
+// through scalar loads).  LDS is used only to transpose pencils; every LDS row has
+// stride lx+1 so that r-pencil and s-pencil accesses avoid bank conflicts.
+// HBM traffic is the algorithmic minimum: each lane reads and writes whole
+// r-pencils (lx contiguous values), i.e. coalesced element-major streams.
+//
+// This file is compiled once per lx (-DSEM_LX=<lx>) so that the per-lx
+// instantiations build in parallel; it exports plain host launchers.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sem_kernels.h"
+
+#ifndef SEM_LX
+#error "compile with -DSEM_LX=<lx>"
+#endif
+
+namespace sem {
+
+// ------------------------------------------------------------------ launch shape
+// Elements per workgroup: fill whole wave64s where possible, keep the two LDS
+// transpose buffers within 64 KB (up to 160 KB for a single large element), and
+// aim at about 256 lanes per workgroup.
+template <int LX, typename T>
+struct Shape {
+    static constexpr int NP = LX * LX;                       // lanes per element
+    static constexpr int PAD = LX + 1;                       // LDS row stride
+    static constexpr int ESZ = NP * PAD;                     // one LDS buffer, one element
+    static constexpr int EBYTES = 2 * ESZ * (int)sizeof(T);  // LDS per element
+    static constexpr int pick()
+    {
+        int best = 1;
+        double best_score = 1e9;
+        for (int e = 1; e * NP <= 1024; ++e) {
+            if (e > 1 && e * EBYTES > 64 * 1024) break;
+            const int thr = e * NP;
+            const int waves = (thr + 63) / 64;
+            const double waste = double(waves * 64 - thr) / double(waves * 64);
+            const double dist = (thr > 256 ? thr - 256 : 256 - thr) / 1024.0;
+            const double score = waste + 0.25 * dist;
+            if (score < best_score - 1e-12) { best_score = score; best = e; }
+        }
+        return best;
+    }
+    static constexpr int EPB = pick();
+    static constexpr int NT = EPB * NP;
+};
+
+template <int LX, typename T>
+struct Lds {
+    T buf[2][Shape<LX, T>::EPB][Shape<LX, T>::ESZ];
+};
+
+// LDS index of point (i, j, k) inside one element buffer.
+template <int LX>
+__device__ __forceinline__ int lidx(int i, int j, int k) { return i + (LX + 1) * (j + LX * k); }
+
+// out[m] = sum_l D[m][l] in[l]   (derivative along the pencil)
+template <int LX, typename T>
+__device__ __forceinline__ void dmul(const DMat<LX, T> &D, const T (&in)[LX], T (&out)[LX])
+{
+#pragma unroll
+    for (int m = 0; m < LX; ++m) {
+        T s = D.d[m * LX] * in[0];
+#pragma unroll
+        for (int l = 1; l < LX; ++l) s = fma(D.d[m * LX + l], in[l], s);
+        out[m] = s;
+    }
+}
+
+// out[m] = sum_l D[l][m] in[l]   (transposed derivative along the pencil)
+template <int LX, typename T>
+__device__ __forceinline__ void dtmul(const DMat<LX, T> &D, const T (&in)[LX], T (&out)[LX])
+{
+#pragma unroll
+    for (int m = 0; m < LX; ++m) {
+        T s = D.d[m] * in[0];
+#pragma unroll
+        for (int l = 1; l < LX; ++l) s = fma(D.d[l * LX + m], in[l], s);
+        out[m] = s;
+    }
+}
+
+// Reference-space gradient of one field held as the lane's r-pencil `u`.
+// Returns ur, us, ut as r-pencils.  Uses both LDS buffers; ends synchronised.
+template <int LX, typename T>
+__device__ __forceinline__ void grad(const DMat<LX, T> &D, const T (&u)[LX], T *s0, T *s1,
+                                     int a, int b, T (&ur)[LX], T (&us)[LX], T (&ut)[LX])
+{
+    dmul<LX, T>(D, u, ur);
+#pragma unroll
+    for (int i = 0; i < LX; ++i) s0[lidx<LX>(i, a, b)] = u[i];
+    __syncthreads();
+    T v[LX], q[LX];
+#pragma unroll
+    for (int l = 0; l < LX; ++l) v[l] = s0[lidx<LX>(a, l, b)];   // s-pencil (i=a, k=b)
+    dmul<LX, T>(D, v, q);
+    T v2[LX], q2[LX];
+#pragma unroll
+    for (int l = 0; l < LX; ++l) v2[l] = s0[lidx<LX>(a, b, l)];  // t-pencil (i=a, j=b)
+    dmul<LX, T>(D, v2, q2);
+#pragma unroll
+    for (int m = 0; m < LX; ++m) s1[lidx<LX>(a, b, m)] = q2[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < LX; ++m) s0[lidx<LX>(a, m, b)] = q[m];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < LX; ++i) {
+        us[i] = s0[lidx<LX>(i, a, b)];
+        ut[i] = s1[lidx<LX>(i, a, b)];
+    }
+    __syncthreads();
+}
+
+// acc = D_r^T wr + D_s^T ws + D_t^T wt for r-pencils wr, ws, wt.  Ends synchronised.
+template <int LX, typename T>
+__device__ __forceinline__ void div(const DMat<LX, T> &D, const T (&wr)[LX], const T (&ws)[LX],
+                                    const T (&wt)[LX], T *s0, T *s1, int a, int b, T (&acc)[LX])
+{
+    dtmul<LX, T>(D, wr, acc);
+#pragma unroll
+    for (int i = 0; i < LX; ++i) {
+        s0[lidx<LX>(i, a, b)] = ws[i];
+        s1[lidx<LX>(i, a, b)] = wt[i];
+    }
+    __syncthreads();
+    T v[LX], q[LX], v2[LX], q2[LX];
+#pragma unroll
+    for (int l = 0; l < LX; ++l) v[l] = s0[lidx<LX>(a, l, b)];
+#pragma unroll
+    for (int l = 0; l < LX; ++l) v2[l] = s1[lidx<LX>(a, b, l)];
+    dtmul<LX, T>(D, v, q);
+    dtmul<LX, T>(D, v2, q2);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < LX; ++m) {
+        s0[lidx<LX>(a, m, b)] = q[m];
+        s1[lidx<LX>(a, b, m)] = q2[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < LX; ++i) acc[i] += s0[lidx<LX>(i, a, b)] + s1[lidx<LX>(i, a, b)];
+    __syncthreads();
+}
+
+template <int LX, typename T>
+__device__ __forceinline__ void load_row(T (&r)[LX], const T *__restrict__ p, bool act)
+{
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < LX; ++i) r[i] = p[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < LX; ++i) r[i] = T(0);
+    }
+}
+
+template <int LX, typename T>
+__device__ __forceinline__ void store_row(T *__restrict__ p, const T (&r)[LX], bool act)
+{
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < LX; ++i) p[i] = r[i];
+    }
+}
+
+// Apply h1 * G at every point of the r-pencil (in place: ur,us,ut -> wr,ws,wt).
+template <int LX, typename T>
+__device__ __forceinline__ void apply_G(const T (&g)[6][LX], const T (&h1)[LX], T (&ur)[LX],
+                                        T (&us)[LX], T (&ut)[LX])
+{
+#pragma unroll
+    for (int i = 0; i < LX; ++i) {
+        const T r = ur[i], s = us[i], t = ut[i];
+        ur[i] = h1[i] * (g[0][i] * r + g[3][i] * s + g[4][i] * t);
+        us[i] = h1[i] * (g[3][i] * r + g[1][i] * s + g[5][i] * t);
+        ut[i] = h1[i] * (g[4][i] * r + g[5][i] * s + g[2][i] * t);
+    }
+}
+
+// ------------------------------------------------------------------ w = A_L u
+// NF fields share one read of G (and B, h1, h2).
+template <int LX, typename T, int NF>
+__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DMat<LX, T> D)
+{
+    using S = Shape<LX, T>;
+    __shared__ Lds<LX, T> lds;
+    const int tid = threadIdx.x;
+    const int slot = tid / S::NP;
+    const int t = tid - slot * S::NP;
+    const int a = t % LX, b = t / LX;
+    const int64_t e = (int64_t)blockIdx.x * S::EPB + slot;
+    const bool act = e < A.nelv;
+    const int64_t row = e * (int64_t)(LX * LX * LX) + (int64_t)LX * t;
+    T *s0 = lds.buf[0][slot], *s1 = lds.buf[1][slot];
+
+    T g[6][LX];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) load_row<LX, T>(g[f], A.G + f * A.n + row, act);
+    T h1[LX], h2b[LX];
+    if (A.h1) load_row<LX, T>(h1, A.h1 + row, act);
+    else {
+#pragma unroll
+        for (int i = 0; i < LX; ++i) h1[i] = A.h1s;
+    }
+    const bool mass = A.h2 != nullptr || A.h2s != T(0);
+    if (mass) {
+        load_row<LX, T>(h2b, A.B + row, act);
+        if (A.h2) {
+            T h2[LX];
+            load_row<LX, T>(h2, A.h2 + row, act);
+#pragma unroll
+            for (int i = 0; i < LX; ++i) h2b[i] *= h2[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < LX; ++i) h2b[i] *= A.h2s;
+        }
+    }
+#pragma unroll 1
+    for (int f = 0; f < NF; ++f) {
+        T u[LX];
+        load_row<LX, T>(u, A.u + f * A.n + row, act);
+        T ur[LX], us[LX], ut[LX];
+        grad<LX, T>(D, u, s0, s1, a, b, ur, us, ut);
+        apply_G<LX, T>(g, h1, ur, us, ut);
+        T w[LX];
+        div<LX, T>(D, ur, us, ut, s0, s1, a, b, w);
+        if (mass) {
+#pragma unroll
+            for (int i = 0; i < LX; ++i) w[i] = fma(h2b[i], u[i], w[i]);
+        }
+        store_row<LX, T>(A.w + f * A.n + row, w, act);
+    }
+}
+
+// ------------------------------------------------------------------ fused CG matvec
+// For each field f (skipped once its solve has stopped):
+//   p = dinv * r + beta_f * p     (beta_f = 0 on the first iteration)
+//   w = A_L p,   partial_f += sum p * w   (the unassembled identity p^T A p = p_L^T A_L p_L)
+// Partials are per workgroup; a separate kernel reduces them in a fixed order.
+template <int LX, typename T, int NF>
+__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DMat<LX, T> D)
+{
+    using S = Shape<LX, T>;
+    __shared__ Lds<LX, T> lds;
+    __shared__ double red[NF][S::NT];
+    const int tid = threadIdx.x;
+    const int slot = tid / S::NP;
+    const int t = tid - slot * S::NP;
+    const int a = t % LX, b = t / LX;
+    const int64_t e = (int64_t)blockIdx.x * S::EPB + slot;
+    const bool act = e < A.nelv;
+    const int64_t row = e * (int64_t)(LX * LX * LX) + (int64_t)LX * t;
+    T *s0 = lds.buf[0][slot], *s1 = lds.buf[1][slot];
+
+    T g[6][LX];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) load_row<LX, T>(g[f], A.G + f * A.n + row, act);
+    T h1[LX], h2b[LX];
+    if (A.h1) load_row<LX, T>(h1, A.h1 + row, act);
+    else {
+#pragma unroll
+        for (int i = 0; i < LX; ++i) h1[i] = A.h1s;
+    }
+    const bool mass = A.h2 != nullptr || A.h2s != T(0);
+    if (mass) {
+        load_row<LX, T>(h2b, A.B + row, act);
+        if (A.h2) {
+            T h2[LX];
+            load_row<LX, T>(h2, A.h2 + row, act);
+#pragma unroll
+            for (int i = 0; i < LX; ++i) h2b[i] *= h2[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < LX; ++i) h2b[i] *= A.h2s;
+        }
+    }
+    T dinv[LX];
+    load_row<LX, T>(dinv, A.dinv + row, act);
+
+    double part[NF];
+#pragma unroll 1
+    for (int f = 0; f < NF; ++f) {
+        part[f] = 0.0;
+        const CgScalars *sc = A.scal + f;
+        if (sc->stop) continue;  // uniform: every lane reads the same flag
+        const T beta = (T)sc->beta;
+        T r[LX], p[LX];
+        load_row<LX, T>(r, A.r + f * A.n + row, act);
+        load_row<LX, T>(p, A.p + f * A.n + row, act);
+#pragma unroll
+        for (int i = 0; i < LX; ++i) p[i] = fma(beta, p[i], dinv[i] * r[i]);
+        store_row<LX, T>(A.p + f * A.n + row, p, act);
+        T ur[LX], us[LX], ut[LX];
+        grad<LX, T>(D, p, s0, s1, a, b, ur, us, ut);
+        apply_G<LX, T>(g, h1, ur, us, ut);
+        T w[LX];
+        div<LX, T>(D, ur, us, ut, s0, s1, a, b, w);
+        if (mass) {
+#pragma unroll
+            for (int i = 0; i < LX; ++i) w[i] = fma(h2b[i], p[i], w[i]);
+        }
+        store_row<LX, T>(A.w + f * A.n + row, w, act);
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < LX; ++i) s += (double)p[i] * (double)w[i];
+        part[f] = s;
+    }
+    // workgroup reduction in a fixed order (deterministic): the first wave (always
+    // full, NT >= 64) sums strided slices, then a butterfly inside that wave.
+#pragma unroll
+    for (int f = 0; f < NF; ++f) red[f][tid] = part[f];
+    __syncthreads();
+    if (tid < 64) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            double v = 0.0;
+            for (int q = tid; q < S::NT; q += 64) v += red[f][q];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (tid == 0) A.partial[(int64_t)f * gridDim.x + blockIdx.x] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ h1-adjoint
+// g = (D v)^T G (D u) per point.
+template <int LX, typename T>
+__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_adjoint(AdjArgs<T> A, DMat<LX, T> D)
+{
+    using S = Shape<LX, T>;
+    __shared__ Lds<LX, T> lds;
+    const int tid = threadIdx.x;
+    const int slot = tid / S::NP;
+    const int t = tid - slot * S::NP;
+    const int a = t % LX, b = t / LX;
+    const int64_t e = (int64_t)blockIdx.x * S::EPB + slot;
+    const bool act = e < A.nelv;
+    const int64_t row = e * (int64_t)(LX * LX * LX) + (int64_t)LX * t;
+    T *s0 = lds.buf[0][slot], *s1 = lds.buf[1][slot];
+
+    T u[LX], v[LX];
+    load_row<LX, T>(u, A.u + row, act);
+    load_row<LX, T>(v, A.v + row, act);
+    T g[6][LX];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) load_row<LX, T>(g[f], A.G + f * A.n + row, act);
+    T ur[LX], us[LX], ut[LX], vr[LX], vs[LX], vt[LX];
+    grad<LX, T>(D, u, s0, s1, a, b, ur, us, ut);
+    grad<LX, T>(D, v, s0, s1, a, b, vr, vs, vt);
+    T out[LX];
+#pragma unroll
+    for (int i = 0; i < LX; ++i) {
+        const T r = ur[i], s = us[i], q = ut[i];
+        out[i] = vr[i] * (g[0][i] * r + g[3][i] * s + g[4][i] * q)
+               + vs[i] * (g[3][i] * r + g[1][i] * s + g[5][i] * q)
+               + vt[i] * (g[4][i] * r + g[5][i] * s + g[2][i] * q);
+    }
+    store_row<LX, T>(A.g + row, out, act);
+}
+
+// ------------------------------------------------------------------ setup kernels
+// Geometric factors from nodal coordinates (isoparametric metric, FP64).
+// One thread per point; plain loops (setup only).
+template <int LX>
+__global__ __launch_bounds__(256) void k_geometry(GeomArgs A, DMat<LX, double> D, WVec<LX> W)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.n) return;
+    constexpr int NPE = LX * LX * LX;
+    const int64_t e = p / NPE;
+    const int q = (int)(p - e * NPE);
+    const int i = q % LX, j = (q / LX) % LX, k = q / (LX * LX);
+    const int64_t b0 = e * NPE;
+    double m[3][3];
+    for (int c = 0; c < 3; ++c) {
+        const double *X = A.xyz + c * A.n + b0;
+        double dr = 0, ds = 0, dt = 0;
+#pragma unroll
+        for (int l = 0; l < LX; ++l) {
+            dr = fma(D.d[i * LX + l], X[l + LX * (j + LX * k)], dr);
+            ds = fma(D.d[j * LX + l], X[i + LX * (l + LX * k)], ds);
+            dt = fma(D.d[k * LX + l], X[i + LX * (j + LX * l)], dt);
+        }
+        m[c][0] = dr;
+        m[c][1] = ds;
+        m[c][2] = dt;
+    }
+    // cofactors: C[c][d] = d(det)/d m[c][d];  inverse: dr_d/dx_c = C[c][d] / J
+    double C[3][3];
+    C[0][0] = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+    C[0][1] = m[1][2] * m[2][0] - m[1][0] * m[2][2];
+    C[0][2] = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+    C[1][0] = m[0][2] * m[2][1] - m[0][1] * m[2][2];
+    C[1][1] = m[0][0] * m[2][2] - m[0][2] * m[2][0];
+    C[1][2] = m[0][1] * m[2][0] - m[0][0] * m[2][1];
+    C[2][0] = m[0][1] * m[1][2] - m[0][2] * m[1][1];
+    C[2][1] = m[0][2] * m[1][0] - m[0][0] * m[1][2];
+    C[2][2] = m[0][0] * m[1][1] - m[0][1] * m[1][0];
+    const double J = m[0][0] * C[0][0] + m[0][1] * C[0][1] + m[0][2] * C[0][2];
+    const double rho = W.w[i] * W.w[j] * W.w[k];
+    // G_ab = rho J sum_c (C[c][a]/J)(C[c][b]/J) = rho/J sum_c C[c][a] C[c][b]
+    const double s = rho / J;
+    const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int f = 0; f < 6; ++f) {
+        const double d = C[0][ia[f]] * C[0][ib[f]] + C[1][ia[f]] * C[1][ib[f]] + C[2][ia[f]] * C[2][ib[f]];
+        A.G[f * A.n + p] = s * d;
+    }
+    A.B[p] = rho * J;
+    if (!(J > 0.0)) atomicAdd(A.nbad, 1u);
+}
+
+// Diagonal of the unassembled operator (point Jacobi), FP64, one thread per point.
+template <int LX>
+__global__ __launch_bounds__(256) void k_diag(DiagArgs A, DMat<LX, double> D)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.n) return;
+    constexpr int NPE = LX * LX * LX;
+    const int64_t e = p / NPE;
+    const int q = (int)(p - e * NPE);
+    const int i = q % LX, j = (q / LX) % LX, k = q / (LX * LX);
+    const int64_t b0 = e * NPE;
+    const double *G = A.G;
+    const int64_t n = A.n;
+    double s = 0.0;
+#pragma unroll
+    for (int l = 0; l < LX; ++l) {
+        const int64_t pr = b0 + l + LX * (j + LX * k);
+        const int64_t ps = b0 + i + LX * (l + LX * k);
+        const int64_t pt = b0 + i + LX * (j + LX * l);
+        const double cr = A.h1 ? A.h1[pr] : A.h1s;
+        const double cs = A.h1 ? A.h1[ps] : A.h1s;
+        const double ct = A.h1 ? A.h1[pt] : A.h1s;
+        const double dri = D.d[l * LX + i], dsj = D.d[l * LX + j], dtk = D.d[l * LX + k];
+        s += dri * dri * cr * G[pr];
+        s += dsj * dsj * cs * G[n + ps];
+        s += dtk * dtk * ct * G[2 * n + pt];
+    }
+    const double c = A.h1 ? A.h1[p] : A.h1s;
+    const double di = D.d[i * LX + i], dj = D.d[j * LX + j], dk = D.d[k * LX + k];
+    s += 2.0 * di * dj * c * G[3 * n + p];
+    s += 2.0 * di * dk * c * G[4 * n + p];
+    s += 2.0 * dj * dk * c * G[5 * n + p];
+    const double c2 = A.h2 ? A.h2[p] : A.h2s;
+    if (c2 != 0.0) s += c2 * A.B[p];
+    A.d[p] = s;
+}
+
+}  // namespace sem
+
+// ------------------------------------------------------------------ host launchers
+#define SEM_PASTE2(a, b) a##b
+#define SEM_PASTE(a, b) SEM_PASTE2(a, b)
+
+namespace {
+template <int LX, typename T>
+sem::DMat<LX, T> make_dmat(const double *D)
+{
+    sem::DMat<LX, T> m;
+    for (int q = 0; q < LX * LX; ++q) m.d[q] = (T)D[q];
+    return m;
+}
+
+template <typename T>
+hipError_t launch_ax(const sem::AxArgs<T> &A, const double *D, int nfields, hipStream_t st)
+{
+    using S = sem::Shape<SEM_LX, T>;
+    const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
+    if (grid == 0) return hipSuccess;
+    const auto Dm = make_dmat<SEM_LX, T>(D);
+    if (nfields == 3)
+        hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 3>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+    else
+        hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg(const sem::CgMatvecArgs<T> &A, const double *D, int nfields, hipStream_t st)
+{
+    using S = sem::Shape<SEM_LX, T>;
+    const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
+    if (grid == 0) return hipSuccess;
+    const auto Dm = make_dmat<SEM_LX, T>(D);
+    if (nfields == 3)
+        hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+    else
+        hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj(const sem::AdjArgs<T> &A, const double *D, hipStream_t st)
+{
+    using S = sem::Shape<SEM_LX, T>;
+    const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL((sem::k_ax_adjoint<SEM_LX, T>), dim3(grid), dim3(S::NT), 0, st, A,
+                       make_dmat<SEM_LX, T>(D));
+    return hipGetLastError();
+}
+}  // namespace
+
+extern "C" {
+
+hipError_t SEM_PASTE(sem_launch_ax_f64_lx, SEM_LX)(const sem::AxArgs<double> *A, const double *D,
+                                                    int nfields, hipStream_t st)
+{
+    return launch_ax<double>(*A, D, nfields, st);
+}
+hipError_t SEM_PASTE(sem_launch_ax_f32_lx, SEM_LX)(const sem::AxArgs<float> *A, const double *D,
+                                                    int nfields, hipStream_t st)
+{
+    return launch_ax<float>(*A, D, nfields, st);
+}
+hipError_t SEM_PASTE(sem_launch_cg_f64_lx, SEM_LX)(const sem::CgMatvecArgs<double> *A,
+                                                    const double *D, int nfields, hipStream_t st)
+{
+    return launch_cg<double>(*A, D, nfields, st);
+}
+hipError_t SEM_PASTE(sem_launch_cg_f32_lx, SEM_LX)(const sem::CgMatvecArgs<float> *A,
+                                                    const double *D, int nfields, hipStream_t st)
+{
+    return launch_cg<float>(*A, D, nfields, st);
+}
+hipError_t SEM_PASTE(sem_launch_adj_f64_lx, SEM_LX)(const sem::AdjArgs<double> *A, const double *D,
+                                                     hipStream_t st)
+{
+    return launch_adj<double>(*A, D, st);
+}
+hipError_t SEM_PASTE(sem_launch_adj_f32_lx, SEM_LX)(const sem::AdjArgs<float> *A, const double *D,
+                                                     hipStream_t st)
+{
+    return launch_adj<float>(*A, D, st);
+}
+hipError_t SEM_PASTE(sem_launch_geom_lx, SEM_LX)(const sem::GeomArgs *A, const double *D,
+                                                  const double *w, hipStream_t st)
+{
+    if (A->n == 0) return hipSuccess;
+    sem::WVec<SEM_LX> W;
+    for (int i = 0; i < SEM_LX; ++i) W.w[i] = w[i];
+    const unsigned grid = (unsigned)((A->n + 255) / 256);
+    hipLaunchKernelGGL((sem::k_geometry<SEM_LX>), dim3(grid), dim3(256), 0, st, *A,
+                       make_dmat<SEM_LX, double>(D), W);
+    return hipGetLastError();
+}
+hipError_t SEM_PASTE(sem_launch_diag_lx, SEM_LX)(const sem::DiagArgs *A, const double *D,
+                                                  hipStream_t st)
+{
+    if (A->n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((A->n + 255) / 256);
+    hipLaunchKernelGGL((sem::k_diag<SEM_LX>), dim3(grid), dim3(256), 0, st, *A,
+                       make_dmat<SEM_LX, double>(D));
+    return hipGetLastError();
+}
+// number of per-workgroup partials the CG matvec writes per field
+int64_t SEM_PASTE(sem_cg_nblocks_f64_lx, SEM_LX)(int64_t nelv)
+{
+    using S = sem::Shape<SEM_LX, double>;
+    return (nelv + S::EPB - 1) / S::EPB;
+}
+int64_t SEM_PASTE(sem_cg_nblocks_f32_lx, SEM_LX)(int64_t nelv)
+{
+    using S = sem::Shape<SEM_LX, float>;
+    return (nelv + S::EPB - 1) / S::EPB;
+}
+}

@@ -1,0 +1,202 @@
+// host_setup.cpp -- host-side setup of libsem: GLL space, synthetic box mesh,
+// gather-scatter maps.  Pure C++ (no device calls), so it also runs on machines
+// without a GPU.
+//
+// GLL space (Jansson et al., arXiv 2107.01243, Section 2, Eq. 7-9): points are
+// -1, +1 and the zeros of L'_N, found with Newton's method on
+// f(x) = x L_N(x) - L_{N-1}(x) (whose zeros in (-1,1) are those of L'_N because
+// (1-x^2) L'_N = N (L_{N-1} - x L_N)), with f'(x) = (N+1) L_N(x); all in long
+// double.  The derivative matrix uses barycentric weights,
+// D_ij = (lambda_j / lambda_i) / (x_i - x_j), D_ii = -sum_{j != i} D_ij.
+//
+// Gather-scatter maps (Section 3.2): local indices are bucketed by global id
+// (counting sort when the id range is compact, comparison sort otherwise), which
+// keeps them in ascending local order inside each id.
+#include "sem_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <thread>
+#include <vector>
+
+namespace semh {
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn)
+{
+    unsigned nt = std::thread::hardware_concurrency();
+    if (nt == 0) nt = 1;
+    if (nt > 32) nt = 32;
+    if (n < 65536 || nt == 1) {
+        fn(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        const int64_t lo = t * chunk, hi = std::min<int64_t>(n, lo + chunk);
+        if (lo >= hi) break;
+        th.emplace_back([=, &fn] { fn(lo, hi); });
+    }
+    for (auto &x : th) x.join();
+}
+
+static void legendre_pair(int N, long double x, long double &LN, long double &LNm1)
+{
+    long double p0 = 1.0L, p1 = x;
+    if (N == 0) { LN = 1.0L; LNm1 = 0.0L; return; }
+    for (int k = 1; k < N; ++k) {
+        const long double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+        p0 = p1;
+        p1 = p2;
+    }
+    LN = p1;
+    LNm1 = p0;
+}
+
+void gll_space(int lx, double *xi, double *w, double *D)
+{
+    const int N = lx - 1;
+    std::vector<long double> x(lx), lam(lx);
+    x[0] = -1.0L;
+    x[N] = 1.0L;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 1; i < N; ++i) {
+        long double t = -cosl(pi * i / N);
+        for (int it = 0; it < 60; ++it) {
+            long double L, Lm;
+            legendre_pair(N, t, L, Lm);
+            const long double dt = (t * L - Lm) / ((N + 1) * L);
+            t -= dt;
+            if (fabsl(dt) < 1e-19L) break;
+        }
+        x[i] = t;
+    }
+    for (int i = 0; i < lx / 2; ++i) {  // exact symmetry about zero
+        const long double a = 0.5L * (x[N - i] - x[i]);
+        x[i] = -a;
+        x[N - i] = a;
+    }
+    if (lx % 2) x[N / 2] = 0.0L;
+    for (int i = 0; i < lx; ++i) {
+        long double L, Lm;
+        legendre_pair(N, x[i], L, Lm);
+        xi[i] = (double)x[i];
+        w[i] = (double)(2.0L / (N * (N + 1.0L) * L * L));
+    }
+    for (int j = 0; j < lx; ++j) {
+        long double p = 1.0L;
+        for (int k = 0; k < lx; ++k)
+            if (k != j) p *= (x[j] - x[k]);
+        lam[j] = 1.0L / p;
+    }
+    for (int i = 0; i < lx; ++i) {
+        long double diag = 0.0L;
+        for (int j = 0; j < lx; ++j) {
+            if (j == i) continue;
+            const long double v = (lam[j] / lam[i]) / (x[i] - x[j]);
+            D[i * lx + j] = (double)v;
+            diag -= v;
+        }
+        D[i * lx + i] = (double)diag;
+    }
+}
+
+void box_mesh(int nx, int ny, int nz, int lx, double eps, const double *xi, int64_t *glb,
+              uint8_t *dir, double *xyz)
+{
+    const int N = lx - 1;
+    const int64_t Mx = (int64_t)nx * N + 1, My = (int64_t)ny * N + 1, Mz = (int64_t)nz * N + 1;
+    const int64_t nelv = (int64_t)nx * ny * nz;
+    const int64_t npe = (int64_t)lx * lx * lx;
+    const int64_t n = nelv * npe;
+    const double two_pi = 2.0 * M_PI;
+    parallel_for(nelv, [&](int64_t e0, int64_t e1) {
+        std::vector<double> sx(lx), sy(lx), sz(lx);
+        for (int64_t e = e0; e < e1; ++e) {
+            const int64_t ex = e % nx, ey = (e / nx) % ny, ez = e / ((int64_t)nx * ny);
+            for (int k = 0; k < lx; ++k)
+                for (int j = 0; j < lx; ++j)
+                    for (int i = 0; i < lx; ++i) {
+                        const int64_t p = e * npe + i + (int64_t)lx * (j + (int64_t)lx * k);
+                        const int64_t gx = ex * N + i, gy = ey * N + j, gz = ez * N + k;
+                        if (glb) glb[p] = gx + Mx * (gy + My * gz);
+                        if (dir)
+                            dir[p] = (gx == 0 || gx == Mx - 1 || gy == 0 || gy == My - 1 || gz == 0 ||
+                                      gz == Mz - 1);
+                        if (xyz) {
+                            const double X = (ex + 0.5 * (xi[i] + 1.0)) / nx;
+                            const double Y = (ey + 0.5 * (xi[j] + 1.0)) / ny;
+                            const double Z = (ez + 0.5 * (xi[k] + 1.0)) / nz;
+                            const double sX = std::sin(two_pi * X), sY = std::sin(two_pi * Y),
+                                         sZ = std::sin(two_pi * Z);
+                            xyz[p] = X + eps * sY * sZ;
+                            xyz[n + p] = Y + eps * sZ * sX;
+                            xyz[2 * n + p] = Z + eps * sX * sY;
+                        }
+                    }
+        }
+    });
+}
+
+// Bucket local indices by global id; returns false (with msg) on invalid input.
+bool build_gs_maps(int64_t n, const int64_t *glb, const uint8_t *dir, GsMaps &m, std::string &msg)
+{
+    m = GsMaps();
+    m.n = n;
+    if (n >= ((int64_t)1 << 31)) { msg = "gather-scatter needs n_local < 2^31"; return false; }
+    int64_t gmax = -1;
+    for (int64_t p = 0; p < n; ++p) {
+        if (glb[p] < 0) { msg = "negative global id"; return false; }
+        gmax = std::max(gmax, glb[p]);
+    }
+    std::vector<int32_t> order(n);
+    std::vector<int64_t> start;  // group boundaries inside `order`
+    std::vector<int64_t> gid;
+    if (n > 0 && gmax <= 4 * n + 1024) {
+        std::vector<int64_t> cnt(gmax + 2, 0);
+        for (int64_t p = 0; p < n; ++p) cnt[glb[p] + 1] += 1;
+        for (int64_t g = 0; g <= gmax; ++g) cnt[g + 1] += cnt[g];
+        std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+        for (int64_t p = 0; p < n; ++p) order[pos[glb[p]]++] = (int32_t)p;
+        for (int64_t g = 0; g <= gmax; ++g)
+            if (cnt[g + 1] > cnt[g]) { start.push_back(cnt[g]); gid.push_back(g); }
+        start.push_back(n);
+    } else if (n > 0) {
+        std::vector<std::pair<int64_t, int32_t>> s(n);
+        for (int64_t p = 0; p < n; ++p) s[p] = {glb[p], (int32_t)p};
+        std::sort(s.begin(), s.end());
+        for (int64_t p = 0; p < n; ++p) {
+            order[p] = s[p].second;
+            if (p == 0 || s[p].first != s[p - 1].first) { start.push_back(p); gid.push_back(s[p].first); }
+        }
+        start.push_back(n);
+    }
+    m.mult.assign(n, 0);
+    m.owner.assign(n, 0);
+    const int64_t ng = (int64_t)gid.size();
+    m.n_unique = ng;
+    m.blk_ptr.push_back(0);
+    for (int64_t g = 0; g < ng; ++g) {
+        const int64_t lo = start[g], hi = start[g + 1], c = hi - lo;
+        if (c > 255) { msg = "more than 255 copies of one global id"; return false; }
+        if (dir) {
+            for (int64_t q = lo + 1; q < hi; ++q)
+                if ((dir[order[q]] != 0) != (dir[order[lo]] != 0)) {
+                    msg = "Dirichlet flag differs between copies of one global id";
+                    return false;
+                }
+        }
+        m.owner[order[lo]] = 1;
+        for (int64_t q = lo; q < hi; ++q) m.mult[order[q]] = (uint8_t)c;
+        if (c == 2) {
+            m.pairs.push_back(order[lo]);
+            m.pairs.push_back(order[lo + 1]);
+        } else if (c > 2) {
+            for (int64_t q = lo; q < hi; ++q) m.blk_idx.push_back(order[q]);
+            m.blk_ptr.push_back((int64_t)m.blk_idx.size());
+        }
+    }
+    return true;
+}
+
+}  // namespace semh

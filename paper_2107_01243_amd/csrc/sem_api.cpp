@@ -1,0 +1,1107 @@
+// sem_api.cpp -- the C ABI of libsem: handles, validation, device residency and the
+// Krylov drivers (Jansson et al., arXiv 2107.01243: Eq. 9-10 operator, Section 3.2
+// gather-scatter, Section 4 Jacobi-preconditioned CG, Section 10 precision outlook).
+//
+// Device residency: the mesh and gather-scatter handles are built on the host and
+// uploaded on first device use, so their host logic (maps, counts, validation)
+// is usable on machines without a GPU.  Everything numeric runs in the HIP
+// kernels of ax_kernels.hip and vec_kernels.hip; the drivers only sequence
+// launches and poll a few device scalars.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sem.h"
+#include "sem_host.h"
+#include "sem_kernels.h"
+#include "vec_kernels.h"
+
+using namespace sem;
+
+// ------------------------------------------------------------------ launcher table
+#define SEM_LX_LIST(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+#define SEM_DECL(L)                                                                                     \
+    extern "C" hipError_t sem_launch_ax_f64_lx##L(const AxArgs<double> *, const double *, int, hipStream_t); \
+    extern "C" hipError_t sem_launch_ax_f32_lx##L(const AxArgs<float> *, const double *, int, hipStream_t);  \
+    extern "C" hipError_t sem_launch_cg_f64_lx##L(const CgMatvecArgs<double> *, const double *, int,        \
+                                                  hipStream_t);                                             \
+    extern "C" hipError_t sem_launch_cg_f32_lx##L(const CgMatvecArgs<float> *, const double *, int,         \
+                                                  hipStream_t);                                             \
+    extern "C" hipError_t sem_launch_adj_f64_lx##L(const AdjArgs<double> *, const double *, hipStream_t);   \
+    extern "C" hipError_t sem_launch_adj_f32_lx##L(const AdjArgs<float> *, const double *, hipStream_t);    \
+    extern "C" hipError_t sem_launch_geom_lx##L(const GeomArgs *, const double *, const double *,           \
+                                                hipStream_t);                                               \
+    extern "C" hipError_t sem_launch_diag_lx##L(const DiagArgs *, const double *, hipStream_t);             \
+    extern "C" int64_t sem_cg_nblocks_f64_lx##L(int64_t);                                                   \
+    extern "C" int64_t sem_cg_nblocks_f32_lx##L(int64_t);
+SEM_LX_LIST(SEM_DECL)
+
+extern "C" {
+unsigned sem_vec_grid(int64_t n);
+hipError_t sem_launch_gs_f64(const GsArgs<double> *, hipStream_t);
+hipError_t sem_launch_gs_f32(const GsArgs<float> *, hipStream_t);
+hipError_t sem_launch_mask(void *, int, const int32_t *, int64_t, int64_t, int, hipStream_t);
+hipError_t sem_launch_fill_f64(double *, double, int64_t, hipStream_t);
+hipError_t sem_launch_fill_f32(float *, float, int64_t, hipStream_t);
+hipError_t sem_launch_cast_f32_f64(float *, const double *, double, int64_t, hipStream_t);
+hipError_t sem_launch_invert(double *, const uint8_t *, int64_t, hipStream_t);
+hipError_t sem_launch_cg_init_f64(const CgInitArgs<double> *, unsigned, hipStream_t);
+hipError_t sem_launch_cg_init_f32(const CgInitArgs<float> *, unsigned, hipStream_t);
+hipError_t sem_launch_cg_start(const CgFinishArgs *, hipStream_t);
+hipError_t sem_launch_cg_update_f64(const CgUpdateArgs<double> *, unsigned, hipStream_t);
+hipError_t sem_launch_cg_update_f32(const CgUpdateArgs<float> *, unsigned, hipStream_t);
+hipError_t sem_launch_cg_finish(const CgFinishArgs *, hipStream_t);
+hipError_t sem_launch_dots(const DotArgs *, unsigned, hipStream_t);
+hipError_t sem_launch_dots_finish(const double *, int64_t, int, double *, hipStream_t);
+hipError_t sem_launch_residual(double *, const double *, const double *, const double *, int64_t, int,
+                               hipStream_t);
+hipError_t sem_launch_fcg_dir(double *, const double *, const double *, const int *, int64_t, int,
+                              hipStream_t);
+hipError_t sem_launch_fcg_update(double *, double *, const double *, const double *, const double *,
+                                 const double *, const int *, int64_t, int, hipStream_t);
+hipError_t sem_launch_fcg_scale_down(float *, const double *, const double *, const int *, int64_t, int,
+                                     hipStream_t);
+hipError_t sem_launch_fcg_scale_up(double *, const float *, const double *, int64_t, int, hipStream_t);
+}
+
+namespace {
+
+struct LxFns {
+    hipError_t (*ax64)(const AxArgs<double> *, const double *, int, hipStream_t);
+    hipError_t (*ax32)(const AxArgs<float> *, const double *, int, hipStream_t);
+    hipError_t (*cg64)(const CgMatvecArgs<double> *, const double *, int, hipStream_t);
+    hipError_t (*cg32)(const CgMatvecArgs<float> *, const double *, int, hipStream_t);
+    hipError_t (*adj64)(const AdjArgs<double> *, const double *, hipStream_t);
+    hipError_t (*adj32)(const AdjArgs<float> *, const double *, hipStream_t);
+    hipError_t (*geom)(const GeomArgs *, const double *, const double *, hipStream_t);
+    hipError_t (*diag)(const DiagArgs *, const double *, hipStream_t);
+    int64_t (*nblk64)(int64_t);
+    int64_t (*nblk32)(int64_t);
+};
+
+const LxFns &fns(int lx)
+{
+#define SEM_ROW(L)                                                                                 \
+    {sem_launch_ax_f64_lx##L, sem_launch_ax_f32_lx##L, sem_launch_cg_f64_lx##L, sem_launch_cg_f32_lx##L, \
+     sem_launch_adj_f64_lx##L, sem_launch_adj_f32_lx##L, sem_launch_geom_lx##L, sem_launch_diag_lx##L,  \
+     sem_cg_nblocks_f64_lx##L, sem_cg_nblocks_f32_lx##L},
+    static const LxFns table[] = {SEM_LX_LIST(SEM_ROW)};
+    return table[lx - SEM_LX_MIN];
+}
+
+thread_local std::string g_err;
+
+sem_status fail(sem_status s, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(x)                                                                                     \
+    do {                                                                                               \
+        hipError_t e_ = (x);                                                                           \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? SEM_ERR_OOM : SEM_ERR_HIP, "%s failed: %s (%s:%d)", \
+                        #x, hipGetErrorString(e_), __FILE__, __LINE__);                                \
+    } while (0)
+
+#define SEM_TRY(x)                          \
+    do {                                    \
+        sem_status s_ = (x);                \
+        if (s_ != SEM_OK) return s_;        \
+    } while (0)
+
+inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+template <typename P>
+sem_status dalloc(P **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) return SEM_OK;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(P));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? SEM_ERR_OOM : SEM_ERR_HIP, "hipMalloc of %zu bytes failed: %s",
+                    count * sizeof(P), hipGetErrorString(e));
+    }
+    return SEM_OK;
+}
+
+template <typename P>
+void dfree(P *&p)
+{
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+sem_status current_device(int *dev)
+{
+    HIP_TRY(hipGetDevice(dev));
+    return SEM_OK;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle types
+struct sem_space_s {
+    int lx;
+    double xi[SEM_LX_MAX], w[SEM_LX_MAX], D[SEM_LX_MAX * SEM_LX_MAX];
+};
+
+struct sem_mesh_s {
+    int64_t nelv = 0;
+    int lx = 0;
+    int64_t n = 0;
+    std::vector<int64_t> glb;
+    std::vector<uint8_t> dir;     // empty when no Dirichlet points
+    std::vector<int32_t> dir_idx; // local indices of Dirichlet points
+    int64_t n_unique = -1;        // filled by the gs builder
+    // device copies (uploaded lazily)
+    int device = -1;
+    uint8_t *d_dir = nullptr;
+    int32_t *d_dir_idx = nullptr;
+};
+
+struct sem_gs_s {
+    sem_mesh msh = nullptr;
+    semh::GsMaps m;
+    int device = -1;
+    int32_t *d_pairs = nullptr;
+    int64_t *d_blk_ptr = nullptr;
+    int32_t *d_blk_idx = nullptr;
+    uint8_t *d_owner = nullptr;
+    int64_t npairs() const { return (int64_t)m.pairs.size() / 2; }
+    int64_t nblocks() const { return (int64_t)m.blk_ptr.size() - 1; }
+};
+
+namespace {
+
+// Scratch owned by a coef handle, grown on demand.
+struct Work {
+    int64_t cap_n = 0;   // points per field the buffers hold
+    int cap_f = 0;       // fields
+    bool mixed = false;
+    double *r = nullptr, *p = nullptr, *w = nullptr;          // CG (FP64)
+    double *z = nullptr, *q = nullptr;                         // flexible CG outer
+    float *r32 = nullptr, *y32 = nullptr, *p32 = nullptr, *w32 = nullptr;  // inner FP32 CG
+    float *ri32 = nullptr;
+    double *partial = nullptr;
+    int64_t partial_len = 0;
+    CgScalars *scal = nullptr;      // device [fields]
+    CgScalars *h_scal = nullptr;    // pinned mirror
+    AlphaJob *job64 = nullptr;      // device, for the FP64 matvec grid
+    AlphaJob *job32 = nullptr;      // device, for the FP32 matvec grid
+    double *dots = nullptr;         // device results of k_dots_finish
+    double *h_dots = nullptr;       // pinned mirror
+    double *fcg = nullptr;          // device: beta[3], alpha[3], norm[3], inv_norm[3]
+    double *h_fcg = nullptr;        // pinned mirror
+    int *done = nullptr;            // device [3]
+    int *h_done = nullptr;          // pinned mirror
+    void release()
+    {
+        dfree(r); dfree(p); dfree(w); dfree(z); dfree(q);
+        dfree(r32); dfree(y32); dfree(p32); dfree(w32); dfree(ri32);
+        dfree(partial); dfree(scal); dfree(job64); dfree(job32); dfree(dots); dfree(fcg); dfree(done);
+        if (h_scal) (void)hipHostFree(h_scal);
+        if (h_dots) (void)hipHostFree(h_dots);
+        if (h_fcg) (void)hipHostFree(h_fcg);
+        if (h_done) (void)hipHostFree(h_done);
+        h_scal = nullptr; h_dots = nullptr; h_fcg = nullptr; h_done = nullptr;
+        cap_n = 0; cap_f = 0; mixed = false; partial_len = 0;
+    }
+};
+
+}  // namespace
+
+struct sem_coef_s {
+    sem_space Xh = nullptr;
+    sem_mesh msh = nullptr;
+    int lx = 0;
+    int64_t n = 0, nelv = 0;
+    int device = -1;
+    unsigned flags = 0;
+    double *G = nullptr, *B = nullptr;
+    float *G32 = nullptr, *B32 = nullptr;
+    double h1s = 1.0, h2s = 0.0;
+    double *h1 = nullptr, *h2 = nullptr;
+    float *h1_32 = nullptr, *h2_32 = nullptr;
+    double *dinv = nullptr;
+    float *dinv32 = nullptr;
+    bool dinv_valid = false;
+    const void *dinv_gs = nullptr;
+    Work ws;
+};
+
+// ------------------------------------------------------------------ small helpers
+namespace {
+
+sem_status check_device(int want)
+{
+    int dev;
+    SEM_TRY(current_device(&dev));
+    if (dev != want) return fail(SEM_ERR_INVALID, "handle belongs to device %d but device %d is current", want, dev);
+    return SEM_OK;
+}
+
+sem_status mesh_upload(sem_mesh m)
+{
+    if (m->device >= 0) return check_device(m->device);
+    int dev;
+    SEM_TRY(current_device(&dev));
+    if (!m->dir.empty()) {
+        SEM_TRY(dalloc(&m->d_dir, m->n));
+        HIP_TRY(hipMemcpy(m->d_dir, m->dir.data(), m->n, hipMemcpyHostToDevice));
+    }
+    if (!m->dir_idx.empty()) {
+        SEM_TRY(dalloc(&m->d_dir_idx, m->dir_idx.size()));
+        HIP_TRY(hipMemcpy(m->d_dir_idx, m->dir_idx.data(), m->dir_idx.size() * 4, hipMemcpyHostToDevice));
+    }
+    m->device = dev;
+    return SEM_OK;
+}
+
+sem_status gs_upload(sem_gs g)
+{
+    if (g->device >= 0) return check_device(g->device);
+    int dev;
+    SEM_TRY(current_device(&dev));
+    const auto &m = g->m;
+    SEM_TRY(dalloc(&g->d_pairs, m.pairs.size()));
+    SEM_TRY(dalloc(&g->d_blk_ptr, m.blk_ptr.size()));
+    SEM_TRY(dalloc(&g->d_blk_idx, m.blk_idx.size()));
+    SEM_TRY(dalloc(&g->d_owner, m.owner.size()));
+    if (!m.pairs.empty()) HIP_TRY(hipMemcpy(g->d_pairs, m.pairs.data(), m.pairs.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_blk_ptr, m.blk_ptr.data(), m.blk_ptr.size() * 8, hipMemcpyHostToDevice));
+    if (!m.blk_idx.empty())
+        HIP_TRY(hipMemcpy(g->d_blk_idx, m.blk_idx.data(), m.blk_idx.size() * 4, hipMemcpyHostToDevice));
+    if (!m.owner.empty()) HIP_TRY(hipMemcpy(g->d_owner, m.owner.data(), m.owner.size(), hipMemcpyHostToDevice));
+    g->device = dev;
+    return SEM_OK;
+}
+
+sem_status check_coef(sem_coef c, sem_mesh msh, sem_space Xh)
+{
+    if (!c || !msh || !Xh) return fail(SEM_ERR_INVALID, "NULL handle");
+    if (c->msh != msh) return fail(SEM_ERR_INVALID, "coef was created for a different mesh");
+    if (c->Xh != Xh) return fail(SEM_ERR_INVALID, "coef was created for a different space");
+    return check_device(c->device);
+}
+
+template <typename T>
+sem_status launch_gs(T *u, int nf, sem_gs g, const CgScalars *skip, const AlphaJob *job, hipStream_t st)
+{
+    GsArgs<T> A;
+    A.u = u;
+    A.pairs = g->d_pairs;
+    A.blk_ptr = g->d_blk_ptr;
+    A.blk_idx = g->d_blk_idx;
+    A.npairs = g->npairs();
+    A.nblocks = g->nblocks();
+    A.n = g->m.n;
+    A.nfields = nf;
+    A.skip = skip;
+    A.alpha_job = job;
+    if (A.npairs + A.nblocks == 0 && job == nullptr) return SEM_OK;
+    hipError_t e;
+    if constexpr (sizeof(T) == 8) e = sem_launch_gs_f64(&A, st);
+    else e = sem_launch_gs_f32(&A, st);
+    HIP_TRY(e);
+    return SEM_OK;
+}
+
+template <typename T>
+sem_status launch_ax(sem_coef c, T *w, const T *u, int nf, hipStream_t st)
+{
+    AxArgs<T> A;
+    A.w = w;
+    A.u = u;
+    A.n = c->n;
+    A.nelv = c->nelv;
+    hipError_t e;
+    if constexpr (sizeof(T) == 8) {
+        A.G = c->G; A.B = c->B; A.h1 = c->h1; A.h2 = c->h2; A.h1s = c->h1s; A.h2s = c->h2s;
+        e = fns(c->lx).ax64(&A, c->Xh->D, nf, st);
+    } else {
+        A.G = c->G32; A.B = c->B32; A.h1 = c->h1_32; A.h2 = c->h2_32;
+        A.h1s = (float)c->h1s; A.h2s = (float)c->h2s;
+        e = fns(c->lx).ax32(&A, c->Xh->D, nf, st);
+    }
+    HIP_TRY(e);
+    return SEM_OK;
+}
+
+// Jacobi inverse (point Jacobi: exact assembled diagonal), cached per (coef, gs).
+sem_status ensure_dinv(sem_coef c, sem_gs g, hipStream_t st)
+{
+    if (c->dinv_valid && c->dinv_gs == (const void *)g) return SEM_OK;
+    if (!c->dinv) SEM_TRY(dalloc(&c->dinv, c->n));
+    DiagArgs A;
+    A.d = c->dinv;
+    A.G = c->G;
+    A.B = c->B;
+    A.h1 = c->h1;
+    A.h2 = c->h2;
+    A.h1s = c->h1s;
+    A.h2s = c->h2s;
+    A.n = c->n;
+    HIP_TRY(fns(c->lx).diag(&A, c->Xh->D, st));
+    SEM_TRY(launch_gs<double>(c->dinv, 1, g, nullptr, nullptr, st));
+    HIP_TRY(sem_launch_invert(c->dinv, c->msh->d_dir, c->n, st));
+    if (c->flags & SEM_COEF_F32) {
+        if (!c->dinv32) SEM_TRY(dalloc(&c->dinv32, c->n));
+        HIP_TRY(sem_launch_cast_f32_f64(c->dinv32, c->dinv, 1.0, c->n, st));
+    }
+    c->dinv_valid = true;
+    c->dinv_gs = g;
+    return SEM_OK;
+}
+
+sem_status ensure_work(sem_coef c, int nf, bool mixed)
+{
+    Work &W = c->ws;
+    if (W.cap_n == c->n && W.cap_f >= nf && (W.mixed || !mixed)) return SEM_OK;
+    W.release();
+    const int64_t n = c->n;
+    const int64_t nn = n * nf;
+    SEM_TRY(dalloc(&W.r, nn));
+    SEM_TRY(dalloc(&W.p, nn));
+    SEM_TRY(dalloc(&W.w, nn));
+    if (mixed) {
+        SEM_TRY(dalloc(&W.z, nn));
+        SEM_TRY(dalloc(&W.q, nn));
+        SEM_TRY(dalloc(&W.r32, nn));
+        SEM_TRY(dalloc(&W.y32, nn));
+        SEM_TRY(dalloc(&W.p32, nn));
+        SEM_TRY(dalloc(&W.w32, nn));
+        SEM_TRY(dalloc(&W.ri32, nn));
+    }
+    const int64_t nb = std::max<int64_t>({fns(c->lx).nblk64(c->nelv), fns(c->lx).nblk32(c->nelv),
+                                          (int64_t)sem_vec_grid(n)});
+    W.partial_len = 4 * (int64_t)nf * nb;
+    SEM_TRY(dalloc(&W.partial, W.partial_len));
+    SEM_TRY(dalloc(&W.scal, nf));
+    SEM_TRY(dalloc(&W.job64, 1));
+    SEM_TRY(dalloc(&W.job32, 1));
+    SEM_TRY(dalloc(&W.dots, 4 * nf));
+    SEM_TRY(dalloc(&W.fcg, 4 * nf));
+    SEM_TRY(dalloc(&W.done, nf));
+    HIP_TRY(hipHostMalloc((void **)&W.h_scal, sizeof(CgScalars) * nf, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&W.h_dots, sizeof(double) * 4 * nf, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&W.h_fcg, sizeof(double) * 4 * nf, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&W.h_done, sizeof(int) * nf, hipHostMallocDefault));
+    const AlphaJob j64{W.partial, fns(c->lx).nblk64(c->nelv), W.scal};
+    const AlphaJob j32{W.partial, fns(c->lx).nblk32(c->nelv), W.scal};
+    HIP_TRY(hipMemcpy(W.job64, &j64, sizeof(AlphaJob), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(W.job32, &j32, sizeof(AlphaJob), hipMemcpyHostToDevice));
+    W.cap_n = n;
+    W.cap_f = nf;
+    W.mixed = mixed;
+    return SEM_OK;
+}
+
+// Owner-weighted dots on the device: out[q*nf + f] = sum_owned a_q b_q (field f).
+sem_status dots(sem_coef c, sem_gs g, int nf, int nd, const double *const *a, const double *const *b,
+                double *host_out, hipStream_t st)
+{
+    Work &W = c->ws;
+    DotArgs A;
+    for (int q = 0; q < 4; ++q) {
+        A.a[q] = q < nd ? a[q] : nullptr;
+        A.b[q] = q < nd ? b[q] : nullptr;
+    }
+    A.owner = g->d_owner;
+    A.partial = W.partial;
+    A.n = c->n;
+    A.nd = nd;
+    A.nfields = nf;
+    const unsigned grid = sem_vec_grid(c->n);
+    HIP_TRY(sem_launch_dots(&A, grid, st));
+    HIP_TRY(sem_launch_dots_finish(W.partial, grid, nd * nf, W.dots, st));
+    HIP_TRY(hipMemcpyAsync(W.h_dots, W.dots, sizeof(double) * nd * nf, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::memcpy(host_out, W.h_dots, sizeof(double) * nd * nf);
+    return SEM_OK;
+}
+
+// Jacobi-PCG in precision T on nf fields.  x is the iterate (zeroed unless use_x0),
+// b the assembled, masked right-hand side.  Per-field results land in W.h_scal.
+template <typename T>
+sem_status cg_run(sem_coef c, sem_gs g, int nf, T *x, const T *b, bool use_x0, T *r, T *p, T *w,
+                  const T *dinv, double rtol, int max_iter, int check_every, double *hist, int hist_len,
+                  hipStream_t st)
+{
+    Work &W = c->ws;
+    const int64_t n = c->n;
+    const bool f64 = sizeof(T) == 8;
+    if (use_x0) {
+        SEM_TRY(launch_ax<T>(c, w, x, nf, st));
+        SEM_TRY(launch_gs<T>(w, nf, g, nullptr, nullptr, st));
+    } else {
+        if constexpr (sizeof(T) == 8) HIP_TRY(sem_launch_fill_f64(x, 0.0, n * nf, st));
+        else HIP_TRY(sem_launch_fill_f32(x, 0.0f, n * nf, st));
+    }
+    for (int f = 0; f < nf; ++f) {
+        CgScalars s{};
+        s.rtol = rtol;
+        s.max_iter = max_iter;
+        W.h_scal[f] = s;
+    }
+    HIP_TRY(hipMemcpyAsync(W.scal, W.h_scal, sizeof(CgScalars) * nf, hipMemcpyHostToDevice, st));
+    const unsigned vg = sem_vec_grid(n);
+    {
+        CgInitArgs<T> A;
+        A.b = b;
+        A.w = use_x0 ? w : nullptr;
+        A.r = r;
+        A.p = p;
+        A.dinv = dinv;
+        A.owner = g->d_owner;
+        A.partial = W.partial;
+        A.n = n;
+        A.nfields = nf;
+        if constexpr (sizeof(T) == 8) HIP_TRY(sem_launch_cg_init_f64(&A, vg, st));
+        else HIP_TRY(sem_launch_cg_init_f32(&A, vg, st));
+        CgFinishArgs F{W.partial, (int64_t)vg, W.scal, hist, hist_len, nf};
+        HIP_TRY(sem_launch_cg_start(&F, st));
+    }
+    const AlphaJob *job = f64 ? W.job64 : W.job32;
+
+    CgMatvecArgs<T> M;
+    M.p = p;
+    M.w = w;
+    M.r = r;
+    M.dinv = dinv;
+    if constexpr (sizeof(T) == 8) {
+        M.G = c->G; M.B = c->B; M.h1 = c->h1; M.h2 = c->h2; M.h1s = c->h1s; M.h2s = c->h2s;
+    } else {
+        M.G = c->G32; M.B = c->B32; M.h1 = c->h1_32; M.h2 = c->h2_32;
+        M.h1s = (float)c->h1s; M.h2s = (float)c->h2s;
+    }
+    M.n = n;
+    M.nelv = c->nelv;
+    M.scal = W.scal;
+    M.partial = W.partial;
+    CgUpdateArgs<T> U{x, r, p, w, dinv, g->d_owner, W.scal, W.partial, n, nf};
+    CgFinishArgs F{W.partial, (int64_t)vg, W.scal, hist, hist_len, nf};
+
+    if (check_every < 1) check_every = 1;
+    const int64_t max_batches = (int64_t)(max_iter + check_every - 1) / check_every + 2;
+    // first poll right after initialisation (b = 0 or an exact initial guess)
+    HIP_TRY(hipMemcpyAsync(W.h_scal, W.scal, sizeof(CgScalars) * nf, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t bt = 0; bt < max_batches; ++bt) {
+        bool all = true;
+        for (int f = 0; f < nf; ++f) all = all && W.h_scal[f].stop;
+        if (all) break;
+        int launched_max = 0;
+        for (int f = 0; f < nf; ++f) launched_max = std::max(launched_max, W.h_scal[f].iter);
+        const int todo = std::min(check_every, std::max(1, max_iter - launched_max));
+        for (int it = 0; it < todo; ++it) {
+            if constexpr (sizeof(T) == 8) HIP_TRY(fns(c->lx).cg64(&M, c->Xh->D, nf, st));
+            else HIP_TRY(fns(c->lx).cg32(&M, c->Xh->D, nf, st));
+            SEM_TRY(launch_gs<T>(w, nf, g, W.scal, job, st));
+            if constexpr (sizeof(T) == 8) HIP_TRY(sem_launch_cg_update_f64(&U, vg, st));
+            else HIP_TRY(sem_launch_cg_update_f32(&U, vg, st));
+            HIP_TRY(sem_launch_cg_finish(&F, st));
+        }
+        HIP_TRY(hipMemcpyAsync(W.h_scal, W.scal, sizeof(CgScalars) * nf, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return SEM_OK;
+}
+
+// True FP64 residual |b - A x| / |b| per field (uses W.w and W.r as scratch).
+sem_status true_residual(sem_coef c, sem_gs g, int nf, const double *x, const double *b, double *rel,
+                         hipStream_t st)
+{
+    Work &W = c->ws;
+    SEM_TRY(launch_ax<double>(c, W.w, x, nf, st));
+    SEM_TRY(launch_gs<double>(W.w, nf, g, nullptr, nullptr, st));
+    HIP_TRY(sem_launch_residual(W.r, b, W.w, c->dinv, c->n, nf, st));
+    const double *a[2] = {W.r, b};
+    double out[6];
+    SEM_TRY(dots(c, g, nf, 2, a, a, out, st));
+    for (int f = 0; f < nf; ++f) {
+        const double rr = out[0 * nf + f], bb = out[1 * nf + f];
+        rel[f] = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    }
+    return SEM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *sem_last_error(void) { return g_err.c_str(); }
+const char *sem_version(void) { return "libsem 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------------ space
+sem_status sem_space_create(int lx, sem_space *Xh)
+{
+    if (!Xh) return fail(SEM_ERR_INVALID, "Xh is NULL");
+    *Xh = nullptr;
+    if (lx < SEM_LX_MIN || lx > SEM_LX_MAX) return fail(SEM_ERR_INVALID, "lx=%d outside [%d, %d]", lx, SEM_LX_MIN, SEM_LX_MAX);
+    sem_space s = new (std::nothrow) sem_space_s();
+    if (!s) return fail(SEM_ERR_OOM, "out of host memory");
+    s->lx = lx;
+    semh::gll_space(lx, s->xi, s->w, s->D);
+    *Xh = s;
+    return SEM_OK;
+}
+
+sem_status sem_space_get(sem_space Xh, double *xi, double *w, double *D)
+{
+    if (!Xh) return fail(SEM_ERR_INVALID, "Xh is NULL");
+    const int lx = Xh->lx;
+    if (xi) std::memcpy(xi, Xh->xi, sizeof(double) * lx);
+    if (w) std::memcpy(w, Xh->w, sizeof(double) * lx);
+    if (D) std::memcpy(D, Xh->D, sizeof(double) * lx * lx);
+    return SEM_OK;
+}
+
+void sem_space_destroy(sem_space Xh) { delete Xh; }
+
+// ------------------------------------------------------------------ box mesh
+sem_status sem_box_mesh(int nx, int ny, int nz, int lx, double eps, int64_t *glb, uint8_t *dirichlet,
+                        double *xyz)
+{
+    if (nx < 1 || ny < 1 || nz < 1) return fail(SEM_ERR_INVALID, "element counts must be >= 1");
+    if (lx < SEM_LX_MIN || lx > SEM_LX_MAX) return fail(SEM_ERR_INVALID, "lx=%d outside [%d, %d]", lx, SEM_LX_MIN, SEM_LX_MAX);
+    if (!(std::fabs(eps) < 0.5)) return fail(SEM_ERR_INVALID, "deformation amplitude must be finite and < 0.5");
+    double xi[SEM_LX_MAX], w[SEM_LX_MAX], D[SEM_LX_MAX * SEM_LX_MAX];
+    semh::gll_space(lx, xi, w, D);
+    semh::box_mesh(nx, ny, nz, lx, eps, xi, glb, dirichlet, xyz);
+    return SEM_OK;
+}
+
+// ------------------------------------------------------------------ mesh
+sem_status sem_mesh_create(int64_t nelv, int lx, const int64_t *glb_host, const uint8_t *dirichlet_host,
+                           sem_mesh *msh)
+{
+    if (!msh) return fail(SEM_ERR_INVALID, "msh is NULL");
+    *msh = nullptr;
+    if (lx < SEM_LX_MIN || lx > SEM_LX_MAX) return fail(SEM_ERR_INVALID, "lx=%d outside [%d, %d]", lx, SEM_LX_MIN, SEM_LX_MAX);
+    if (nelv < 0) return fail(SEM_ERR_INVALID, "nelv < 0");
+    const int64_t n = nelv * (int64_t)lx * lx * lx;
+    if (n > 0 && !glb_host) return fail(SEM_ERR_INVALID, "glb is NULL");
+    if (n >= ((int64_t)1 << 31)) return fail(SEM_ERR_INVALID, "n_local = %lld exceeds 2^31-1", (long long)n);
+    sem_mesh m = new (std::nothrow) sem_mesh_s();
+    if (!m) return fail(SEM_ERR_OOM, "out of host memory");
+    m->nelv = nelv;
+    m->lx = lx;
+    m->n = n;
+    m->glb.assign(glb_host, glb_host + n);
+    for (int64_t p = 0; p < n; ++p)
+        if (m->glb[p] < 0) {
+            delete m;
+            return fail(SEM_ERR_INVALID, "negative global id at %lld", (long long)p);
+        }
+    if (dirichlet_host) {
+        m->dir.resize(n);
+        for (int64_t p = 0; p < n; ++p) {
+            m->dir[p] = dirichlet_host[p] ? 1 : 0;
+            if (m->dir[p]) m->dir_idx.push_back((int32_t)p);
+        }
+        if (m->dir_idx.empty()) m->dir.clear();
+    }
+    *msh = m;
+    return SEM_OK;
+}
+
+sem_status sem_mesh_size(sem_mesh msh, int64_t *nelv, int *lx, int64_t *n_local, int64_t *n_unique,
+                         int64_t *n_dirichlet_local)
+{
+    if (!msh) return fail(SEM_ERR_INVALID, "msh is NULL");
+    if (nelv) *nelv = msh->nelv;
+    if (lx) *lx = msh->lx;
+    if (n_local) *n_local = msh->n;
+    if (n_unique) {
+        if (msh->n_unique < 0) {
+            std::vector<int64_t> s(msh->glb);
+            std::sort(s.begin(), s.end());
+            msh->n_unique = (int64_t)(std::unique(s.begin(), s.end()) - s.begin());
+        }
+        *n_unique = msh->n_unique;
+    }
+    if (n_dirichlet_local) *n_dirichlet_local = (int64_t)msh->dir_idx.size();
+    return SEM_OK;
+}
+
+void sem_mesh_destroy(sem_mesh msh)
+{
+    if (!msh) return;
+    dfree(msh->d_dir);
+    dfree(msh->d_dir_idx);
+    delete msh;
+}
+
+// ------------------------------------------------------------------ gather-scatter
+sem_status sem_gs_create(sem_mesh msh, sem_gs *gs)
+{
+    if (!gs) return fail(SEM_ERR_INVALID, "gs is NULL");
+    *gs = nullptr;
+    if (!msh) return fail(SEM_ERR_INVALID, "msh is NULL");
+    sem_gs g = new (std::nothrow) sem_gs_s();
+    if (!g) return fail(SEM_ERR_OOM, "out of host memory");
+    std::string msg;
+    if (!semh::build_gs_maps(msh->n, msh->glb.data(), msh->dir.empty() ? nullptr : msh->dir.data(), g->m, msg)) {
+        delete g;
+        return fail(SEM_ERR_INVALID, "%s", msg.c_str());
+    }
+    g->msh = msh;
+    msh->n_unique = g->m.n_unique;
+    *gs = g;
+    return SEM_OK;
+}
+
+sem_status sem_gs_sizes(sem_gs gs, int64_t *npairs, int64_t *nblocks, int64_t *nblock_entries)
+{
+    if (!gs) return fail(SEM_ERR_INVALID, "gs is NULL");
+    if (npairs) *npairs = gs->npairs();
+    if (nblocks) *nblocks = gs->nblocks();
+    if (nblock_entries) *nblock_entries = (int64_t)gs->m.blk_idx.size();
+    return SEM_OK;
+}
+
+sem_status sem_gs_export_maps(sem_gs gs, int32_t *pairs, int64_t *blk_ptr, int32_t *blk_idx, uint8_t *mult)
+{
+    if (!gs) return fail(SEM_ERR_INVALID, "gs is NULL");
+    const auto &m = gs->m;
+    if (pairs && !m.pairs.empty()) std::memcpy(pairs, m.pairs.data(), m.pairs.size() * 4);
+    if (blk_ptr) std::memcpy(blk_ptr, m.blk_ptr.data(), m.blk_ptr.size() * 8);
+    if (blk_idx && !m.blk_idx.empty()) std::memcpy(blk_idx, m.blk_idx.data(), m.blk_idx.size() * 4);
+    if (mult && !m.mult.empty()) std::memcpy(mult, m.mult.data(), m.mult.size());
+    return SEM_OK;
+}
+
+void sem_gs_destroy(sem_gs gs)
+{
+    if (!gs) return;
+    dfree(gs->d_pairs);
+    dfree(gs->d_blk_ptr);
+    dfree(gs->d_blk_idx);
+    dfree(gs->d_owner);
+    delete gs;
+}
+
+sem_status sem_gs_op(void *u, int nfields, sem_gs gs, sem_dtype dt, void *stream)
+{
+    if (!gs) return fail(SEM_ERR_INVALID, "gs is NULL");
+    if (nfields != 1 && nfields != 3) return fail(SEM_ERR_INVALID, "nfields must be 1 or 3");
+    if (dt != SEM_F64 && dt != SEM_F32) return fail(SEM_ERR_INVALID, "bad dtype");
+    if (!u && gs->m.n > 0) return fail(SEM_ERR_INVALID, "u is NULL");
+    SEM_TRY(gs_upload(gs));
+    if (dt == SEM_F64) return launch_gs<double>((double *)u, nfields, gs, nullptr, nullptr, S(stream));
+    return launch_gs<float>((float *)u, nfields, gs, nullptr, nullptr, S(stream));
+}
+
+sem_status sem_mask(void *u, int nfields, sem_mesh msh, sem_dtype dt, void *stream)
+{
+    if (!msh) return fail(SEM_ERR_INVALID, "msh is NULL");
+    if (nfields != 1 && nfields != 3) return fail(SEM_ERR_INVALID, "nfields must be 1 or 3");
+    if (dt != SEM_F64 && dt != SEM_F32) return fail(SEM_ERR_INVALID, "bad dtype");
+    if (!u && msh->n > 0) return fail(SEM_ERR_INVALID, "u is NULL");
+    SEM_TRY(mesh_upload(msh));
+    HIP_TRY(sem_launch_mask(u, dt == SEM_F32, msh->d_dir_idx, (int64_t)msh->dir_idx.size(), msh->n, nfields,
+                            S(stream)));
+    return SEM_OK;
+}
+
+// ------------------------------------------------------------------ coef
+static sem_status coef_alloc(sem_space Xh, sem_mesh msh, unsigned flags, sem_coef *out)
+{
+    if (!out) return fail(SEM_ERR_INVALID, "coef is NULL");
+    *out = nullptr;
+    if (!Xh || !msh) return fail(SEM_ERR_INVALID, "NULL handle");
+    if (Xh->lx != msh->lx) return fail(SEM_ERR_INVALID, "space lx=%d but mesh lx=%d", Xh->lx, msh->lx);
+    if (flags & ~SEM_COEF_F32) return fail(SEM_ERR_INVALID, "unknown flags 0x%x", flags);
+    SEM_TRY(mesh_upload(msh));
+    sem_coef c = new (std::nothrow) sem_coef_s();
+    if (!c) return fail(SEM_ERR_OOM, "out of host memory");
+    c->Xh = Xh;
+    c->msh = msh;
+    c->lx = Xh->lx;
+    c->n = msh->n;
+    c->nelv = msh->nelv;
+    c->flags = flags;
+    c->device = msh->device;
+    sem_status s;
+    if ((s = dalloc(&c->G, 6 * c->n)) != SEM_OK || (s = dalloc(&c->B, c->n)) != SEM_OK) {
+        sem_coef_destroy(c);
+        return s;
+    }
+    if (flags & SEM_COEF_F32) {
+        if ((s = dalloc(&c->G32, 6 * c->n)) != SEM_OK || (s = dalloc(&c->B32, c->n)) != SEM_OK) {
+            sem_coef_destroy(c);
+            return s;
+        }
+    }
+    *out = c;
+    return SEM_OK;
+}
+
+static sem_status coef_finish(sem_coef c, hipStream_t st)
+{
+    if (c->flags & SEM_COEF_F32) {
+        HIP_TRY(sem_launch_cast_f32_f64(c->G32, c->G, 1.0, 6 * c->n, st));
+        HIP_TRY(sem_launch_cast_f32_f64(c->B32, c->B, 1.0, c->n, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return SEM_OK;
+}
+
+sem_status sem_coef_create(sem_space Xh, sem_mesh msh, const double *xyz_dev, unsigned flags, void *stream,
+                           sem_coef *coef)
+{
+    if (!xyz_dev && msh && msh->n > 0) return fail(SEM_ERR_INVALID, "xyz is NULL");
+    SEM_TRY(coef_alloc(Xh, msh, flags, coef));
+    sem_coef c = *coef;
+    hipStream_t st = S(stream);
+    unsigned *nbad = nullptr;
+    sem_status s = dalloc(&nbad, 1);
+    if (s != SEM_OK) { sem_coef_destroy(c); *coef = nullptr; return s; }
+    unsigned hbad = 0;
+    hipError_t e = hipMemcpyAsync(nbad, &hbad, sizeof(unsigned), hipMemcpyHostToDevice, st);
+    GeomArgs A{xyz_dev, c->G, c->B, nbad, c->n};
+    if (e == hipSuccess) e = fns(c->lx).geom(&A, Xh->D, Xh->w, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, nbad, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(nbad);
+    if (e != hipSuccess) {
+        sem_coef_destroy(c);
+        *coef = nullptr;
+        return fail(SEM_ERR_HIP, "geometry setup failed: %s", hipGetErrorString(e));
+    }
+    if (hbad) {
+        sem_coef_destroy(c);
+        *coef = nullptr;
+        return fail(SEM_ERR_INVALID, "%u points have a non-positive Jacobian", hbad);
+    }
+    s = coef_finish(c, st);
+    if (s != SEM_OK) { sem_coef_destroy(c); *coef = nullptr; }
+    return s;
+}
+
+sem_status sem_coef_create_from_G(sem_space Xh, sem_mesh msh, const double *G6_dev, const double *B_dev,
+                                  unsigned flags, void *stream, sem_coef *coef)
+{
+    if ((!G6_dev || !B_dev) && msh && msh->n > 0) return fail(SEM_ERR_INVALID, "G or B is NULL");
+    SEM_TRY(coef_alloc(Xh, msh, flags, coef));
+    sem_coef c = *coef;
+    hipStream_t st = S(stream);
+    hipError_t e = hipSuccess;
+    if (c->n > 0) {
+        e = hipMemcpyAsync(c->G, G6_dev, sizeof(double) * 6 * c->n, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->B, B_dev, sizeof(double) * c->n, hipMemcpyDeviceToDevice, st);
+    }
+    if (e != hipSuccess) {
+        sem_coef_destroy(c);
+        *coef = nullptr;
+        return fail(SEM_ERR_HIP, "copy of G/B failed: %s", hipGetErrorString(e));
+    }
+    sem_status s = coef_finish(c, st);
+    if (s != SEM_OK) { sem_coef_destroy(c); *coef = nullptr; }
+    return s;
+}
+
+sem_status sem_coef_set_helmholtz(sem_coef c, const double *h1_dev, double h1, const double *h2_dev, double h2,
+                                  void *stream)
+{
+    if (!c) return fail(SEM_ERR_INVALID, "coef is NULL");
+    SEM_TRY(check_device(c->device));
+    if (!h1_dev && !std::isfinite(h1)) return fail(SEM_ERR_INVALID, "h1 is not finite");
+    if (!h2_dev && !std::isfinite(h2)) return fail(SEM_ERR_INVALID, "h2 is not finite");
+    hipStream_t st = S(stream);
+    const bool f32 = c->flags & SEM_COEF_F32;
+    if (h1_dev) {
+        if (!c->h1) SEM_TRY(dalloc(&c->h1, c->n));
+        HIP_TRY(hipMemcpyAsync(c->h1, h1_dev, sizeof(double) * c->n, hipMemcpyDeviceToDevice, st));
+        if (f32) {
+            if (!c->h1_32) SEM_TRY(dalloc(&c->h1_32, c->n));
+            HIP_TRY(sem_launch_cast_f32_f64(c->h1_32, c->h1, 1.0, c->n, st));
+        }
+    } else {
+        dfree(c->h1);
+        dfree(c->h1_32);
+        c->h1s = h1;
+    }
+    if (h2_dev) {
+        if (!c->h2) SEM_TRY(dalloc(&c->h2, c->n));
+        HIP_TRY(hipMemcpyAsync(c->h2, h2_dev, sizeof(double) * c->n, hipMemcpyDeviceToDevice, st));
+        if (f32) {
+            if (!c->h2_32) SEM_TRY(dalloc(&c->h2_32, c->n));
+            HIP_TRY(sem_launch_cast_f32_f64(c->h2_32, c->h2, 1.0, c->n, st));
+        }
+    } else {
+        dfree(c->h2);
+        dfree(c->h2_32);
+        c->h2s = h2;
+    }
+    c->dinv_valid = false;
+    return SEM_OK;
+}
+
+sem_status sem_coef_export(sem_coef c, double *G6_dev, double *B_dev, void *stream)
+{
+    if (!c) return fail(SEM_ERR_INVALID, "coef is NULL");
+    SEM_TRY(check_device(c->device));
+    if (G6_dev) HIP_TRY(hipMemcpyAsync(G6_dev, c->G, sizeof(double) * 6 * c->n, hipMemcpyDeviceToDevice, S(stream)));
+    if (B_dev) HIP_TRY(hipMemcpyAsync(B_dev, c->B, sizeof(double) * c->n, hipMemcpyDeviceToDevice, S(stream)));
+    return SEM_OK;
+}
+
+void sem_coef_destroy(sem_coef c)
+{
+    if (!c) return;
+    c->ws.release();
+    dfree(c->G); dfree(c->B); dfree(c->G32); dfree(c->B32);
+    dfree(c->h1); dfree(c->h2); dfree(c->h1_32); dfree(c->h2_32);
+    dfree(c->dinv); dfree(c->dinv32);
+    delete c;
+}
+
+// ------------------------------------------------------------------ operators
+sem_status sem_ax_helm(void *w, const void *u, sem_coef coef, sem_mesh msh, sem_space Xh, int nfields,
+                       sem_dtype dt, void *stream)
+{
+    SEM_TRY(check_coef(coef, msh, Xh));
+    if (nfields != 1 && nfields != 3) return fail(SEM_ERR_INVALID, "nfields must be 1 or 3");
+    if (dt != SEM_F64 && dt != SEM_F32) return fail(SEM_ERR_INVALID, "bad dtype");
+    if (dt == SEM_F32 && !(coef->flags & SEM_COEF_F32)) return fail(SEM_ERR_INVALID, "SEM_F32 needs a coef created with SEM_COEF_F32");
+    const size_t bytes = (size_t)coef->n * nfields * (dt == SEM_F64 ? 8 : 4);
+    if (bytes == 0) return SEM_OK;
+    if (!w || !u) return fail(SEM_ERR_INVALID, "w or u is NULL");
+    if (overlap(w, bytes, u, bytes)) return fail(SEM_ERR_INVALID, "w and u overlap");
+    if (dt == SEM_F64) return launch_ax<double>(coef, (double *)w, (const double *)u, nfields, S(stream));
+    return launch_ax<float>(coef, (float *)w, (const float *)u, nfields, S(stream));
+}
+
+sem_status sem_ax_helm_adjoint(void *g, const void *u, const void *v, sem_coef coef, sem_mesh msh,
+                               sem_space Xh, sem_dtype dt, void *stream)
+{
+    SEM_TRY(check_coef(coef, msh, Xh));
+    if (dt != SEM_F64 && dt != SEM_F32) return fail(SEM_ERR_INVALID, "bad dtype");
+    if (dt == SEM_F32 && !(coef->flags & SEM_COEF_F32)) return fail(SEM_ERR_INVALID, "SEM_F32 needs a coef created with SEM_COEF_F32");
+    const size_t bytes = (size_t)coef->n * (dt == SEM_F64 ? 8 : 4);
+    if (bytes == 0) return SEM_OK;
+    if (!g || !u || !v) return fail(SEM_ERR_INVALID, "g, u or v is NULL");
+    if (overlap(g, bytes, u, bytes) || overlap(g, bytes, v, bytes)) return fail(SEM_ERR_INVALID, "g overlaps u or v");
+    hipError_t e;
+    if (dt == SEM_F64) {
+        AdjArgs<double> A{(double *)g, (const double *)u, (const double *)v, coef->G, coef->n, coef->nelv};
+        e = fns(coef->lx).adj64(&A, Xh->D, S(stream));
+    } else {
+        AdjArgs<float> A{(float *)g, (const float *)u, (const float *)v, coef->G32, coef->n, coef->nelv};
+        e = fns(coef->lx).adj32(&A, Xh->D, S(stream));
+    }
+    HIP_TRY(e);
+    return SEM_OK;
+}
+
+sem_status sem_jacobi_inverse(double *dinv, sem_coef coef, sem_mesh msh, sem_space Xh, sem_gs gs, void *stream)
+{
+    SEM_TRY(check_coef(coef, msh, Xh));
+    if (!gs || gs->msh != msh) return fail(SEM_ERR_INVALID, "gs is NULL or built for another mesh");
+    if (!dinv && coef->n > 0) return fail(SEM_ERR_INVALID, "dinv is NULL");
+    SEM_TRY(gs_upload(gs));
+    SEM_TRY(ensure_dinv(coef, gs, S(stream)));
+    if (coef->n > 0)
+        HIP_TRY(hipMemcpyAsync(dinv, coef->dinv, sizeof(double) * coef->n, hipMemcpyDeviceToDevice, S(stream)));
+    return SEM_OK;
+}
+
+// ------------------------------------------------------------------ solver
+static sem_status pcg_fp64(double *x, const double *b, int nf, sem_coef c, sem_gs g, const sem_pcg_params *P,
+                           sem_pcg_info *info, hipStream_t st)
+{
+    Work &W = c->ws;
+    SEM_TRY(cg_run<double>(c, g, nf, x, b, P->use_x0 != 0, W.r, W.p, W.w, c->dinv, P->rtol, P->max_iter,
+                           P->check_every, nullptr, 0, st));
+    CgScalars res[3];
+    std::memcpy(res, W.h_scal, sizeof(CgScalars) * nf);
+    double tr[3];
+    SEM_TRY(true_residual(c, g, nf, x, b, tr, st));
+    sem_status out = SEM_OK;
+    for (int f = 0; f < nf; ++f) {
+        const CgScalars &s = res[f];
+        const double rel = s.bb == 0.0 ? 0.0 : std::sqrt(s.rr / s.bb);
+        const bool conv = s.status == 0 && std::isfinite(rel) && (P->rtol <= 0 || rel <= P->rtol);
+        if (info) {
+            info[f].iters = s.iter;
+            info[f].inner_iters = 0;
+            info[f].converged = conv ? 1 : 0;
+            info[f].rel_res = rel;
+            info[f].true_rel_res = tr[f];
+        }
+        if (s.status == 2) out = fail(SEM_ERR_BREAKDOWN, "CG breakdown in field %d at iteration %d", f, s.iter);
+        else if (!conv && out == SEM_OK)
+            out = fail(SEM_ERR_NOT_CONVERGED, "field %d: |r|/|b| = %.3e after %d iterations", f, rel, s.iter);
+    }
+    return out;
+}
+
+// Flexible CG, FP64 outer iteration, preconditioned by an FP32 Jacobi-PCG solve.
+static sem_status pcg_mixed(double *x, const double *b, int nf, sem_coef c, sem_gs g, const sem_pcg_params *P,
+                            sem_pcg_info *info, hipStream_t st)
+{
+    Work &W = c->ws;
+    const int64_t n = c->n;
+    const int64_t nn = n * nf;
+    // r = b - A x
+    if (P->use_x0) {
+        SEM_TRY(launch_ax<double>(c, W.w, x, nf, st));
+        SEM_TRY(launch_gs<double>(W.w, nf, g, nullptr, nullptr, st));
+        HIP_TRY(sem_launch_residual(W.r, b, W.w, c->dinv, n, nf, st));
+    } else {
+        HIP_TRY(sem_launch_fill_f64(x, 0.0, nn, st));
+        HIP_TRY(hipMemcpyAsync(W.r, b, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+    }
+    HIP_TRY(sem_launch_fill_f64(W.p, 0.0, nn, st));
+    double bb[3], rr[3], pq_old[3] = {0, 0, 0};
+    {
+        const double *a[2] = {b, W.r};
+        double out[6];
+        SEM_TRY(dots(c, g, nf, 2, a, a, out, st));
+        for (int f = 0; f < nf; ++f) { bb[f] = out[f]; rr[f] = out[nf + f]; }
+    }
+    int done[3] = {0, 0, 0}, status[3] = {0, 0, 0}, iters[3] = {0, 0, 0}, inner[3] = {0, 0, 0};
+    for (int f = 0; f < nf; ++f) {
+        if (!std::isfinite(bb[f]) || !std::isfinite(rr[f])) { done[f] = 1; status[f] = 2; }
+        else if (bb[f] == 0.0 || (P->rtol > 0 && std::sqrt(rr[f] / bb[f]) <= P->rtol)) done[f] = 1;
+    }
+    for (int k = 0; k < P->max_iter; ++k) {
+        bool all = true;
+        for (int f = 0; f < nf; ++f) all = all && done[f];
+        if (all) break;
+        // z = |r| * P32(r / |r|)
+        for (int f = 0; f < nf; ++f) {
+            const double nr = std::sqrt(rr[f]);
+            W.h_fcg[2 * nf + f] = nr;
+            W.h_fcg[3 * nf + f] = (done[f] || nr == 0.0) ? 0.0 : 1.0 / nr;
+            W.h_done[f] = done[f];
+        }
+        HIP_TRY(hipMemcpyAsync(W.fcg, W.h_fcg, sizeof(double) * 4 * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(W.done, W.h_done, sizeof(int) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(sem_launch_fcg_scale_down(W.r32, W.r, W.fcg + 3 * nf, W.done, n, nf, st));
+        SEM_TRY(cg_run<float>(c, g, nf, W.y32, W.r32, false, W.ri32, W.p32, W.w32, c->dinv32, P->inner_rtol,
+                              P->inner_max_iter, std::max(1, P->check_every), nullptr, 0, st));
+        for (int f = 0; f < nf; ++f) inner[f] += W.h_scal[f].iter;
+        HIP_TRY(sem_launch_fcg_scale_up(W.z, W.y32, W.fcg + 2 * nf, n, nf, st));
+        // p = z - beta p,  beta = (z, q_old) / (p_old, q_old)
+        if (k == 0) {
+            for (int f = 0; f < nf; ++f) W.h_fcg[f] = 0.0;
+        } else {
+            const double *a[1] = {W.z}, *bq[1] = {W.q};
+            double zq[3];
+            SEM_TRY(dots(c, g, nf, 1, a, bq, zq, st));
+            for (int f = 0; f < nf; ++f) W.h_fcg[f] = pq_old[f] != 0.0 ? zq[f] / pq_old[f] : 0.0;
+        }
+        HIP_TRY(hipMemcpyAsync(W.fcg, W.h_fcg, sizeof(double) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(sem_launch_fcg_dir(W.p, W.z, W.fcg, W.done, n, nf, st));
+        // q = A p
+        SEM_TRY(launch_ax<double>(c, W.q, W.p, nf, st));
+        SEM_TRY(launch_gs<double>(W.q, nf, g, nullptr, nullptr, st));
+        double pq[3], pr[3];
+        {
+            const double *a[2] = {W.p, W.p}, *bq[2] = {W.q, W.r};
+            double out[6];
+            SEM_TRY(dots(c, g, nf, 2, a, bq, out, st));
+            for (int f = 0; f < nf; ++f) { pq[f] = out[f]; pr[f] = out[nf + f]; }
+        }
+        for (int f = 0; f < nf; ++f) {
+            if (done[f]) { W.h_fcg[nf + f] = 0.0; continue; }
+            if (!(pq[f] > 0.0) || !std::isfinite(pq[f]) || !std::isfinite(pr[f])) {
+                done[f] = 1;
+                status[f] = 2;
+                W.h_fcg[nf + f] = 0.0;
+                continue;
+            }
+            W.h_fcg[nf + f] = pr[f] / pq[f];
+            pq_old[f] = pq[f];
+        }
+        for (int f = 0; f < nf; ++f) W.h_done[f] = done[f];
+        HIP_TRY(hipMemcpyAsync(W.fcg + nf, W.h_fcg + nf, sizeof(double) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(W.done, W.h_done, sizeof(int) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(sem_launch_fcg_update(x, W.r, W.p, W.q, c->dinv, W.fcg + nf, W.done, n, nf, st));
+        {
+            const double *a[1] = {W.r};
+            double out[3];
+            SEM_TRY(dots(c, g, nf, 1, a, a, out, st));
+            for (int f = 0; f < nf; ++f) {
+                if (done[f]) continue;
+                rr[f] = out[f];
+                iters[f] += 1;
+                const double rel = std::sqrt(rr[f] / bb[f]);
+                if (!std::isfinite(rel)) { done[f] = 1; status[f] = 2; }
+                else if (P->rtol > 0 && rel <= P->rtol) done[f] = 1;
+            }
+        }
+    }
+    double tr[3];
+    SEM_TRY(true_residual(c, g, nf, x, b, tr, st));
+    sem_status out = SEM_OK;
+    for (int f = 0; f < nf; ++f) {
+        const double rel = bb[f] == 0.0 ? 0.0 : std::sqrt(rr[f] / bb[f]);
+        const bool conv = status[f] == 0 && std::isfinite(rel) && (P->rtol <= 0 || rel <= P->rtol);
+        if (info) {
+            info[f].iters = iters[f];
+            info[f].inner_iters = inner[f];
+            info[f].converged = conv ? 1 : 0;
+            info[f].rel_res = rel;
+            info[f].true_rel_res = tr[f];
+        }
+        if (status[f] == 2) out = fail(SEM_ERR_BREAKDOWN, "flexible CG breakdown in field %d", f);
+        else if (!conv && out == SEM_OK)
+            out = fail(SEM_ERR_NOT_CONVERGED, "field %d: |r|/|b| = %.3e after %d outer iterations", f, rel, iters[f]);
+    }
+    return out;
+}
+
+sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef, sem_mesh msh, sem_space Xh,
+                         sem_gs gs, const sem_pcg_params *params, sem_pcg_info *info, void *stream)
+{
+    SEM_TRY(check_coef(coef, msh, Xh));
+    if (!gs || gs->msh != msh) return fail(SEM_ERR_INVALID, "gs is NULL or built for another mesh");
+    if (!params) return fail(SEM_ERR_INVALID, "params is NULL");
+    if (nfields != 1 && nfields != 3) return fail(SEM_ERR_INVALID, "nfields must be 1 or 3");
+    const sem_pcg_params &P = *params;
+    if (P.max_iter < 1) return fail(SEM_ERR_INVALID, "max_iter must be >= 1");
+    if (!std::isfinite(P.rtol)) return fail(SEM_ERR_INVALID, "rtol is not finite");
+    if (P.mixed) {
+        if (!(coef->flags & SEM_COEF_F32)) return fail(SEM_ERR_INVALID, "mixed solve needs a coef created with SEM_COEF_F32");
+        if (!(P.inner_rtol > 0.0 && P.inner_rtol < 1.0)) return fail(SEM_ERR_INVALID, "inner_rtol must be in (0, 1)");
+        if (P.inner_max_iter < 1) return fail(SEM_ERR_INVALID, "inner_max_iter must be >= 1");
+        if (P.rtol <= 0) return fail(SEM_ERR_INVALID, "mixed solve needs rtol > 0");
+    }
+    const size_t bytes = (size_t)coef->n * nfields * 8;
+    if (bytes == 0) return SEM_OK;
+    if (!x || !b) return fail(SEM_ERR_INVALID, "x or b is NULL");
+    if (overlap(x, bytes, b, bytes)) return fail(SEM_ERR_INVALID, "x and b overlap");
+    hipStream_t st = S(stream);
+    SEM_TRY(gs_upload(gs));
+    SEM_TRY(ensure_dinv(coef, gs, st));
+    SEM_TRY(ensure_work(coef, nfields, P.mixed != 0));
+    if (P.mixed) return pcg_mixed(x, b, nfields, coef, gs, &P, info, st);
+    return pcg_fp64(x, b, nfields, coef, gs, &P, info, st);
+}
+
+}  // extern "C"

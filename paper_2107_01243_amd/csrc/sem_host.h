@@ -1,0 +1,27 @@
+// sem_host.h -- host-side helpers of libsem (internal).
+#pragma once
+#include <stdint.h>
+
+#include <functional>
+#include <string>
+#include <vector>
+
+namespace semh {
+
+struct GsMaps {
+    int64_t n = 0;
+    int64_t n_unique = 0;
+    std::vector<int32_t> pairs;    // (a, b) with a < b, ascending global id
+    std::vector<int64_t> blk_ptr;  // CSR over blocks of >2 copies, ascending global id
+    std::vector<int32_t> blk_idx;  // ascending local index inside a block
+    std::vector<uint8_t> mult;     // copies of each local point's global id
+    std::vector<uint8_t> owner;    // 1 on the lowest local index of every global id
+};
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn);
+void gll_space(int lx, double *xi, double *w, double *D);
+void box_mesh(int nx, int ny, int nz, int lx, double eps, const double *xi, int64_t *glb,
+              uint8_t *dir, double *xyz);
+bool build_gs_maps(int64_t n, const int64_t *glb, const uint8_t *dir, GsMaps &m, std::string &msg);
+
+}  // namespace semh

@@ -1,0 +1,95 @@
+// sem_kernels.h -- argument blocks shared by the HIP kernels and the host driver
+// of libsem (internal; not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sem {
+
+// 1-D GLL derivative matrix d[i*LX + l] = l_l'(xi_i), passed by value so that it
+// sits in the kernel-argument segment and is read with scalar loads.
+template <int LX, typename T>
+struct DMat {
+    T d[LX * LX];
+};
+
+template <int LX>
+struct WVec {
+    double w[LX];
+};
+
+// w = A_L u
+template <typename T>
+struct AxArgs {
+    T *w;
+    const T *u;
+    const T *G;   // 6 planes of n
+    const T *B;   // n (read only when the mass term is active)
+    const T *h1;  // n or nullptr (then h1s)
+    const T *h2;  // n or nullptr (then h2s)
+    T h1s, h2s;
+    int64_t n;    // points per field
+    int64_t nelv;
+};
+
+// Per-field scalars of one CG solve, resident in device memory.
+struct CgScalars {
+    double rz;      // (r, z) of the current iterate
+    double alpha;
+    double beta;    // used by the next matvec: p = z + beta p
+    double rr;      // (r, r)
+    double bb;      // (b, b)
+    double rtol;
+    int iter;       // iterations completed
+    int max_iter;
+    int stop;       // nonzero: this field's iterates are frozen
+    int status;     // 0 running/converged, 1 not converged, 2 breakdown
+};
+
+// p = dinv r + beta p;  w = A_L p;  per-workgroup partial sums of p.w
+template <typename T>
+struct CgMatvecArgs {
+    T *p;
+    T *w;
+    const T *r;
+    const T *dinv;
+    const T *G;
+    const T *B;
+    const T *h1;
+    const T *h2;
+    T h1s, h2s;
+    int64_t n;
+    int64_t nelv;
+    const CgScalars *scal;  // one per field
+    double *partial;        // [field][workgroup]
+};
+
+template <typename T>
+struct AdjArgs {
+    T *g;
+    const T *u;
+    const T *v;
+    const T *G;
+    int64_t n;
+    int64_t nelv;
+};
+
+struct GeomArgs {
+    const double *xyz;  // 3 planes of n
+    double *G;          // 6 planes of n
+    double *B;
+    unsigned *nbad;     // count of points with J <= 0
+    int64_t n;
+};
+
+struct DiagArgs {
+    double *d;
+    const double *G;
+    const double *B;
+    const double *h1;
+    const double *h2;
+    double h1s, h2s;
+    int64_t n;
+};
+
+}  // namespace sem

@@ -1,0 +1,77 @@
+// vec_kernels.h -- argument blocks of the gather-scatter and Krylov-vector kernels
+// (internal to libsem).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sem_kernels.h"
+
+namespace sem {
+
+// Step length of CG folded into the gather-scatter launch: alpha_f = rz_f / pw_f.
+struct AlphaJob {
+    const double *partial;  // [field][nblk] partial sums of p.A_L p
+    int64_t nblk;
+    CgScalars *scal;
+};
+
+template <typename T>
+struct GsArgs {
+    T *u;
+    const int32_t *pairs;    // 2 * npairs
+    const int64_t *blk_ptr;  // nblocks + 1
+    const int32_t *blk_idx;
+    int64_t npairs, nblocks;
+    int64_t n;               // points per field
+    int nfields;
+    const CgScalars *skip;   // optional: fields with skip[f].stop are left untouched
+    const AlphaJob *alpha_job;  // optional (device pointer)
+};
+
+template <typename T>
+struct CgInitArgs {
+    const T *b;
+    const T *w;       // QQ^T A_L x0, or nullptr when x0 = 0
+    T *r;
+    T *p;
+    const T *dinv;
+    const uint8_t *owner;
+    double *partial;  // [3][field][grid]
+    int64_t n;
+    int nfields;
+};
+
+template <typename T>
+struct CgUpdateArgs {
+    T *x;
+    T *r;
+    const T *p;
+    const T *w;
+    const T *dinv;
+    const uint8_t *owner;
+    const CgScalars *scal;
+    double *partial;  // [2][field][grid]
+    int64_t n;
+    int nfields;
+};
+
+struct CgFinishArgs {
+    const double *partial;
+    int64_t nblk;
+    CgScalars *scal;
+    double *hist;     // optional [field][hist_len] relative residual history
+    int hist_len;
+    int nfields;
+};
+
+struct DotArgs {
+    const double *a[4];
+    const double *b[4];
+    const uint8_t *owner;
+    double *partial;  // [nd][field][grid]
+    int64_t n;
+    int nd;
+    int nfields;
+};
+
+}  // namespace sem

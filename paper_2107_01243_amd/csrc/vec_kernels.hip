@@ -1,0 +1,488 @@
+// vec_kernels.hip -- gather-scatter, masking and Krylov-vector kernels of libsem (gfx950).
+//
+// Gather-scatter QQ^T (Jansson et al., arXiv 2107.01243, Eq. 10 and the local
+// gather + scatter of Algorithm 1): ids with two copies are a pair list (the
+// "injective" ids of Section 3.2), ids with more copies are CSR blocks.  One lane
+// per pair / block sums the copies in ascending local order starting from +0 and
+// writes the sum back, so the result is deterministic and bit-reproducible.
+//
+// CG / flexible-CG vector kernels: streaming, one point per lane per step with
+// grid-stride loops, FP64 accumulation of every inner product, per-workgroup
+// partial sums reduced afterwards in a fixed order by a single workgroup
+// (deterministic; no floating-point atomics).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "sem_kernels.h"
+#include "vec_kernels.h"
+
+namespace sem {
+
+constexpr int VT = 256;  // lanes per workgroup of the streaming kernels
+
+// Reduce `nblk` partials per field (layout [field][nblk]) in a fixed order.
+// Runs inside one workgroup of VT lanes; returns the sum on lane 0.
+__device__ double block_sum_fixed(const double *part, int64_t nblk, double *sh)
+{
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int64_t q = tid; q < nblk; q += VT) s += part[q];
+    sh[tid] = s;
+    __syncthreads();
+    for (int w = VT / 2; w > 0; w >>= 1) {
+        if (tid < w) sh[tid] += sh[tid + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------------ gather-scatter
+template <typename T>
+__global__ __launch_bounds__(VT) void k_gs(GsArgs<T> A)
+{
+    const int64_t tid = (int64_t)blockIdx.x * VT + threadIdx.x;
+    for (int f = 0; f < A.nfields; ++f) {
+        if (A.skip && A.skip[f].stop) continue;
+        T *u = A.u + f * A.n;
+        if (tid < A.npairs) {
+            const int32_t a = A.pairs[2 * tid], b = A.pairs[2 * tid + 1];
+            const T s = (T(0) + u[a]) + u[b];
+            u[a] = s;
+            u[b] = s;
+        } else if (tid < A.npairs + A.nblocks) {
+            const int64_t g = tid - A.npairs;
+            const int64_t lo = A.blk_ptr[g], hi = A.blk_ptr[g + 1];
+            T s = T(0);
+            for (int64_t c = lo; c < hi; ++c) s += u[A.blk_idx[c]];
+            for (int64_t c = lo; c < hi; ++c) u[A.blk_idx[c]] = s;
+        }
+    }
+    // Optional fold of the CG step length: alpha_f = rz_f / (p, A p)_f from the
+    // matvec's partials (complete, since that kernel ended before this one began).
+    if (A.alpha_job && blockIdx.x == 0) {
+        __shared__ double sh[VT];
+        const AlphaJob &J = *A.alpha_job;
+        for (int f = 0; f < A.nfields; ++f) {
+            const double pw = block_sum_fixed(J.partial + f * J.nblk, J.nblk, sh);
+            if (threadIdx.x == 0) {
+                CgScalars &s = J.scal[f];
+                if (!s.stop) {
+                    if (!(pw > 0.0) || !isfinite(pw) || !isfinite(s.rz)) {
+                        s.stop = 1;
+                        s.status = 2;
+                        s.alpha = 0.0;
+                    } else {
+                        s.alpha = s.rz / pw;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// u[idx] = 0 for every listed index, each field.
+template <typename T>
+__global__ __launch_bounds__(VT) void k_mask(T *u, const int32_t *idx, int64_t m, int64_t n, int nfields)
+{
+    const int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (t >= m) return;
+    for (int f = 0; f < nfields; ++f) u[f * n + idx[t]] = T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(VT) void k_fill(T *u, T v, int64_t m)
+{
+    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < m; t += (int64_t)gridDim.x * VT)
+        u[t] = v;
+}
+
+// dst = (TD)(scale * src)
+template <typename TD, typename TS>
+__global__ __launch_bounds__(VT) void k_cast(TD *dst, const TS *src, double scale, int64_t m)
+{
+    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < m; t += (int64_t)gridDim.x * VT)
+        dst[t] = (TD)(scale * (double)src[t]);
+}
+
+// ------------------------------------------------------------------ Jacobi inverse
+// dinv = 1/d (d already summed over copies), 0 on Dirichlet points.
+__global__ __launch_bounds__(VT) void k_invert(double *d, const uint8_t *dir, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (t >= n) return;
+    d[t] = (dir && dir[t]) ? 0.0 : 1.0 / d[t];
+}
+
+// ------------------------------------------------------------------ CG kernels
+// Initial residual: r = b - w (w = QQ^T A_L x0), zero where dinv == 0 (Dirichlet);
+// p = 0; partials of (r, dinv r), (r, r), (b, b) over owned points.
+template <typename T>
+__global__ __launch_bounds__(VT) void k_cg_init(CgInitArgs<T> A)
+{
+    __shared__ double sh[3][VT];
+    const int f = blockIdx.y;
+    const T *b = A.b + f * A.n;
+    const T *w = A.w ? A.w + f * A.n : nullptr;
+    T *r = A.r + f * A.n;
+    T *p = A.p + f * A.n;
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < A.n; t += (int64_t)gridDim.x * VT) {
+        const T di = A.dinv[t];
+        const T bi = b[t];
+        const T ri = (di != T(0)) ? (w ? bi - w[t] : bi) : T(0);
+        r[t] = ri;
+        p[t] = T(0);
+        if (A.owner[t]) {
+            rz += (double)ri * (double)(di * ri);
+            rr += (double)ri * (double)ri;
+            bb += (double)bi * (double)bi;
+        }
+    }
+    sh[0][threadIdx.x] = rz;
+    sh[1][threadIdx.x] = rr;
+    sh[2][threadIdx.x] = bb;
+    __syncthreads();
+    for (int s = VT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) A.partial[((int64_t)q * A.nfields + f) * gridDim.x + blockIdx.x] = sh[q][0];
+}
+
+// Finish the initial reductions: rz, rr, bb; beta = 0; stop at once when b = 0
+// or the initial guess already meets the tolerance.
+__global__ __launch_bounds__(VT) void k_cg_start(CgFinishArgs A)
+{
+    __shared__ double sh[VT];
+    for (int f = 0; f < A.nfields; ++f) {
+        const double rz = block_sum_fixed(A.partial + (0 * A.nfields + f) * A.nblk, A.nblk, sh);
+        const double rr = block_sum_fixed(A.partial + (1 * A.nfields + f) * A.nblk, A.nblk, sh);
+        const double bb = block_sum_fixed(A.partial + (2 * A.nfields + f) * A.nblk, A.nblk, sh);
+        if (threadIdx.x == 0) {
+            CgScalars &s = A.scal[f];
+            s.rz = rz;
+            s.rr = rr;
+            s.bb = bb;
+            s.beta = 0.0;
+            s.alpha = 0.0;
+            s.iter = 0;
+            s.status = 0;
+            s.stop = 0;
+            const double rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            if (A.hist) A.hist[(int64_t)f * A.hist_len] = rel;
+            if (!isfinite(bb) || !isfinite(rr) || !isfinite(rz)) { s.stop = 1; s.status = 2; }
+            else if (bb == 0.0 || (s.rtol > 0.0 && rel <= s.rtol)) s.stop = 1;
+            else if (s.max_iter <= 0) { s.stop = 1; s.status = 1; }
+        }
+    }
+}
+
+// x += alpha p; r -= alpha w (not on Dirichlet points); partials of (r, dinv r), (r, r).
+template <typename T>
+__global__ __launch_bounds__(VT) void k_cg_update(CgUpdateArgs<T> A)
+{
+    __shared__ double sh[2][VT];
+    const int f = blockIdx.y;
+    const CgScalars &sc = A.scal[f];
+    double rz = 0.0, rr = 0.0;
+    if (!sc.stop) {
+        const T alpha = (T)sc.alpha;
+        T *x = A.x + f * A.n;
+        T *r = A.r + f * A.n;
+        const T *p = A.p + f * A.n;
+        const T *w = A.w + f * A.n;
+        for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < A.n; t += (int64_t)gridDim.x * VT) {
+            const T di = A.dinv[t];
+            x[t] = fma(alpha, p[t], x[t]);
+            T ri = r[t];
+            if (di != T(0)) {
+                ri = fma(-alpha, w[t], ri);
+                r[t] = ri;
+            }
+            if (A.owner[t]) {
+                rz += (double)ri * (double)(di * ri);
+                rr += (double)ri * (double)ri;
+            }
+        }
+    }
+    sh[0][threadIdx.x] = rz;
+    sh[1][threadIdx.x] = rr;
+    __syncthreads();
+    for (int s = VT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        A.partial[((int64_t)0 * A.nfields + f) * gridDim.x + blockIdx.x] = sh[0][0];
+        A.partial[((int64_t)1 * A.nfields + f) * gridDim.x + blockIdx.x] = sh[1][0];
+    }
+}
+
+// End of one CG iteration: beta = rz_new / rz_old, convergence and iteration cap.
+__global__ __launch_bounds__(VT) void k_cg_finish(CgFinishArgs A)
+{
+    __shared__ double sh[VT];
+    for (int f = 0; f < A.nfields; ++f) {
+        const double rz = block_sum_fixed(A.partial + (0 * A.nfields + f) * A.nblk, A.nblk, sh);
+        const double rr = block_sum_fixed(A.partial + (1 * A.nfields + f) * A.nblk, A.nblk, sh);
+        if (threadIdx.x == 0) {
+            CgScalars &s = A.scal[f];
+            if (!s.stop) {
+                s.iter += 1;
+                s.rr = rr;
+                const double rel = sqrt(rr / s.bb);
+                if (A.hist && s.iter < A.hist_len) A.hist[(int64_t)f * A.hist_len + s.iter] = rel;
+                s.beta = rz / s.rz;
+                s.rz = rz;
+                if (s.rtol > 0.0 && rel <= s.rtol) s.stop = 1;
+                else if (!isfinite(rr) || !isfinite(rz)) { s.stop = 1; s.status = 2; }
+                else if (rz == 0.0) s.stop = 1;
+                else if (s.iter >= s.max_iter) { s.stop = 1; s.status = (s.rtol > 0.0) ? 1 : 0; }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ generic dots
+// partial[q][f][block] for q in 0..nd-1: sum over owned points of a_q * b_q (FP64).
+__global__ __launch_bounds__(VT) void k_dots(DotArgs A)
+{
+    __shared__ double sh[4][VT];
+    const int f = blockIdx.y;
+    double acc[4] = {0, 0, 0, 0};
+    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < A.n; t += (int64_t)gridDim.x * VT) {
+        if (!A.owner[t]) continue;
+        for (int q = 0; q < A.nd; ++q) acc[q] += A.a[q][f * A.n + t] * A.b[q][f * A.n + t];
+    }
+    for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = VT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < A.nd; ++q)
+            A.partial[((int64_t)q * A.nfields + f) * gridDim.x + blockIdx.x] = sh[q][0];
+}
+
+// out[q*nfields + f] = sum of partials, fixed order.
+__global__ __launch_bounds__(VT) void k_dots_finish(const double *partial, int64_t nblk, int nq,
+                                                     double *out)
+{
+    __shared__ double sh[VT];
+    for (int q = 0; q < nq; ++q) {
+        const double s = block_sum_fixed(partial + q * nblk, nblk, sh);
+        if (threadIdx.x == 0) out[q] = s;
+    }
+}
+
+// r = b - w masked (dinv == 0 marks Dirichlet points); used for true residuals.
+__global__ __launch_bounds__(VT) void k_residual(double *r, const double *b, const double *w,
+                                                 const double *dinv, int64_t n, int nfields)
+{
+    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT) {
+        const double di = dinv[t];
+        for (int f = 0; f < nfields; ++f)
+            r[f * n + t] = (di != 0.0) ? b[f * n + t] - w[f * n + t] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ flexible CG (outer, FP64)
+// p = z - beta_f p   (beta_f from coef[f]);  fields with coef[f] flagged done are left alone.
+__global__ __launch_bounds__(VT) void k_fcg_dir(double *p, const double *z, const double *beta,
+                                                const int *done, int64_t n, int nfields)
+{
+    const int f = blockIdx.y;
+    if (done[f]) return;
+    const double bf = beta[f];
+    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT)
+        p[f * n + t] = z[f * n + t] - bf * p[f * n + t];
+}
+
+// x += alpha p; r -= alpha q (not on Dirichlet points).
+__global__ __launch_bounds__(VT) void k_fcg_update(double *x, double *r, const double *p,
+                                                   const double *q, const double *dinv,
+                                                   const double *alpha, const int *done, int64_t n,
+                                                   int nfields)
+{
+    const int f = blockIdx.y;
+    if (done[f]) return;
+    const double a = alpha[f];
+    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT) {
+        x[f * n + t] = fma(a, p[f * n + t], x[f * n + t]);
+        if (dinv[t] != 0.0) r[f * n + t] = fma(-a, q[f * n + t], r[f * n + t]);
+    }
+}
+
+// r32 = (float)(r / |r|_f)  per field (fields flagged done get 0).
+__global__ __launch_bounds__(VT) void k_fcg_scale_down(float *r32, const double *r,
+                                                       const double *inv_norm, const int *done,
+                                                       int64_t n, int nfields)
+{
+    const int f = blockIdx.y;
+    const double s = done[f] ? 0.0 : inv_norm[f];
+    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT)
+        r32[f * n + t] = (float)(s * r[f * n + t]);
+}
+
+// z = |r|_f * (double) y32
+__global__ __launch_bounds__(VT) void k_fcg_scale_up(double *z, const float *y32, const double *norm,
+                                                     int64_t n, int nfields)
+{
+    const int f = blockIdx.y;
+    const double s = norm[f];
+    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT)
+        z[f * n + t] = s * (double)y32[f * n + t];
+}
+
+}  // namespace sem
+
+// ------------------------------------------------------------------ host launchers
+using namespace sem;
+
+static unsigned stream_grid(int64_t n, unsigned cap = 16384)
+{
+    int64_t g = (n + VT - 1) / VT;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+extern "C" {
+
+unsigned sem_vec_grid(int64_t n) { return stream_grid(n); }
+
+hipError_t sem_launch_gs_f64(const GsArgs<double> *A, hipStream_t st)
+{
+    const int64_t work = A->npairs + A->nblocks;
+    const unsigned grid = (unsigned)((work + VT - 1) / VT > 0 ? (work + VT - 1) / VT : 1);
+    hipLaunchKernelGGL(k_gs<double>, dim3(grid), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_gs_f32(const GsArgs<float> *A, hipStream_t st)
+{
+    const int64_t work = A->npairs + A->nblocks;
+    const unsigned grid = (unsigned)((work + VT - 1) / VT > 0 ? (work + VT - 1) / VT : 1);
+    hipLaunchKernelGGL(k_gs<float>, dim3(grid), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_mask(void *u, int is_f32, const int32_t *idx, int64_t m, int64_t n, int nfields,
+                           hipStream_t st)
+{
+    if (m == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((m + VT - 1) / VT);
+    if (is_f32)
+        hipLaunchKernelGGL(k_mask<float>, dim3(grid), dim3(VT), 0, st, (float *)u, idx, m, n, nfields);
+    else
+        hipLaunchKernelGGL(k_mask<double>, dim3(grid), dim3(VT), 0, st, (double *)u, idx, m, n, nfields);
+    return hipGetLastError();
+}
+hipError_t sem_launch_fill_f64(double *u, double v, int64_t m, hipStream_t st)
+{
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<double>, dim3(stream_grid(m)), dim3(VT), 0, st, u, v, m);
+    return hipGetLastError();
+}
+hipError_t sem_launch_fill_f32(float *u, float v, int64_t m, hipStream_t st)
+{
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<float>, dim3(stream_grid(m)), dim3(VT), 0, st, u, v, m);
+    return hipGetLastError();
+}
+hipError_t sem_launch_cast_f32_f64(float *dst, const double *src, double scale, int64_t m, hipStream_t st)
+{
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_cast<float, double>), dim3(stream_grid(m)), dim3(VT), 0, st, dst, src, scale, m);
+    return hipGetLastError();
+}
+hipError_t sem_launch_invert(double *d, const uint8_t *dir, int64_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_invert, dim3((unsigned)((n + VT - 1) / VT)), dim3(VT), 0, st, d, dir, n);
+    return hipGetLastError();
+}
+hipError_t sem_launch_cg_init_f64(const CgInitArgs<double> *A, unsigned grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_init<double>, dim3(grid, A->nfields), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_cg_init_f32(const CgInitArgs<float> *A, unsigned grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_init<float>, dim3(grid, A->nfields), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_cg_start(const CgFinishArgs *A, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_cg_update_f64(const CgUpdateArgs<double> *A, unsigned grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_update<double>, dim3(grid, A->nfields), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_cg_update_f32(const CgUpdateArgs<float> *A, unsigned grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_update<float>, dim3(grid, A->nfields), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_cg_finish(const CgFinishArgs *A, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_dots(const DotArgs *A, unsigned grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dots, dim3(grid, A->nfields), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_dots_finish(const double *partial, int64_t nblk, int nq, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dots_finish, dim3(1), dim3(VT), 0, st, partial, nblk, nq, out);
+    return hipGetLastError();
+}
+hipError_t sem_launch_residual(double *r, const double *b, const double *w, const double *dinv,
+                               int64_t n, int nfields, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_residual, dim3(stream_grid(n)), dim3(VT), 0, st, r, b, w, dinv, n, nfields);
+    return hipGetLastError();
+}
+hipError_t sem_launch_fcg_dir(double *p, const double *z, const double *beta, const int *done,
+                              int64_t n, int nfields, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fcg_dir, dim3(stream_grid(n), nfields), dim3(VT), 0, st, p, z, beta, done, n, nfields);
+    return hipGetLastError();
+}
+hipError_t sem_launch_fcg_update(double *x, double *r, const double *p, const double *q,
+                                 const double *dinv, const double *alpha, const int *done,
+                                 int64_t n, int nfields, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fcg_update, dim3(stream_grid(n), nfields), dim3(VT), 0, st, x, r, p, q, dinv,
+                       alpha, done, n, nfields);
+    return hipGetLastError();
+}
+hipError_t sem_launch_fcg_scale_down(float *r32, const double *r, const double *inv_norm,
+                                     const int *done, int64_t n, int nfields, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fcg_scale_down, dim3(stream_grid(n), nfields), dim3(VT), 0, st, r32, r,
+                       inv_norm, done, n, nfields);
+    return hipGetLastError();
+}
+hipError_t sem_launch_fcg_scale_up(double *z, const float *y32, const double *norm, int64_t n,
+                                   int nfields, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fcg_scale_up, dim3(stream_grid(n), nfields), dim3(VT), 0, st, z, y32, norm,
+                       n, nfields);
+    return hipGetLastError();
+}
+
+}  // extern "C"

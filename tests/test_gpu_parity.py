@@ -1,0 +1,376 @@
+"""GPU parity: libsem's HIP path against the FP64 CPU oracle, through the C ABI.
+
+Each side builds its own GLL space, mesh coordinates and geometric factors from
+the same workload parameters; only the seeded random inputs are shared.
+Tolerances: gather-scatter and maps bit-exact; FP64 arithmetic
+|w - w_ref|_inf / |w_ref|_inf <= 1e-12; FP32 operator vs FP64 oracle <= 2e-6;
+solves as stated per test.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import workloads  # noqa: E402
+from paper_2107_01243_amd import sem  # noqa: E402
+from paper_2107_01243_amd import HelmholtzSolve  # noqa: E402
+
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_inf(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def host(t):
+    return t.detach().to("cpu", torch.float64).numpy()
+
+
+_cache = {}
+
+
+def pair(nx, lx, eps=0.05, fp32=True):
+    """(GPU BoxProblem, oracle Problem) for the same box."""
+    key = (nx, lx, eps, fp32)
+    if key not in _cache:
+        say(f"[build] nx={nx} lx={lx} eps={eps}")
+        _cache.clear()
+        P = sem.BoxProblem.build(nx, lx, eps, fp32=fp32)
+        O = oracle.Problem(nx, lx, eps)
+        _cache[key] = (P, O)
+    return _cache[key]
+
+
+# ------------------------------------------------------------------ geometry + operator
+@pytest.mark.parametrize("nx,lx,eps", [(4, 6, 0.0), (3, 8, 0.05), (2, 12, 0.05), (3, 2, 0.05), (2, 3, 0.05),
+                                       (2, 5, 0.05), (2, 7, 0.05), (2, 9, 0.05), (2, 10, 0.05), (1, 11, 0.05),
+                                       (1, 13, 0.05), (1, 14, 0.05), (1, 15, 0.05), (1, 16, 0.05)])
+def test_geometry_and_ax_fp64(nx, lx, eps):
+    say(f"[ax f64] nx={nx} lx={lx}")
+    P, O = pair(nx, lx, eps)
+    G, B = P.coef.export()
+    torch.cuda.synchronize()
+    assert rel_inf(host(G).reshape(6, -1), O.G) <= 1e-12
+    assert rel_inf(host(B), O.B) <= 1e-12
+    u = workloads.uniform(P.n, workloads.SEED_U)
+    for h1, h2 in [(1.0, 0.0), ("field", "field"), (0.37, 25.0)]:
+        if h1 == "field":
+            h1v = np.exp(0.5 * workloads.uniform(P.n, 5))
+            h2v = 10.0 + workloads.uniform(P.n, 6)
+            P.coef.set_helmholtz(to_dev(h1v), to_dev(h2v))
+            O.set_coef(h1v, h2v)
+        else:
+            P.coef.set_helmholtz(h1, h2)
+            O.set_coef(h1, h2)
+        w = host(P.ax(to_dev(u)))
+        wr = O.ax_local(u)
+        assert rel_inf(w, wr) <= 1e-12, (h1, h2, rel_inf(w, wr))
+    P.coef.set_helmholtz(1.0, 0.0)
+
+
+@pytest.mark.parametrize("nx,lx", [(3, 8), (2, 12), (4, 6)])
+def test_ax_fp32_and_batched(nx, lx):
+    say(f"[ax f32/batched] nx={nx} lx={lx}")
+    P, O = pair(nx, lx)
+    h1v = np.exp(0.5 * workloads.uniform(P.n, 5))
+    P.coef.set_helmholtz(to_dev(h1v), 7.0)
+    O.set_coef(h1v, 7.0)
+    us = [workloads.uniform(P.n, s) for s in workloads.SEED_RHS_FIELDS]
+    refs = [O.ax_local(u) for u in us]
+    # FP32 operator (FP32 G, B, D, h1) against the FP64 oracle
+    u32 = to_dev(us[0], torch.float32)
+    w32 = host(P.ax(u32))
+    assert rel_inf(w32, refs[0]) <= 2e-6
+    # three fields in one launch == three single launches (bit-exact) and == oracle
+    U = to_dev(np.concatenate(us))
+    W = host(P.ax(U, nfields=3)).reshape(3, -1)
+    for f in range(3):
+        single = host(P.ax(to_dev(us[f])))
+        np.testing.assert_array_equal(W[f], single)
+        assert rel_inf(W[f], refs[f]) <= 1e-12
+    U32 = to_dev(np.concatenate(us), torch.float32)
+    W32 = host(P.ax(U32, nfields=3)).reshape(3, -1)
+    for f in range(3):
+        assert rel_inf(W32[f], refs[f]) <= 2e-6
+    P.coef.set_helmholtz(1.0, 0.0)
+
+
+def test_ax_full_size_32cubed_lx8_sampled():
+    """32^3 curved elements, lx = 8, in the benchmark's launch shape: sampled elements
+    recomputed by the oracle from its own coordinates and geometry."""
+    wl = workloads.WORKLOADS["poisson_32x32x32_lx8"]
+    say("[ax full] building 32^3 lx=8")
+    _cache.clear()
+    P = sem.BoxProblem.build(wl.nx, wl.lx, wl.eps)
+    u = workloads.uniform(P.n, workloads.SEED_U)
+    w = host(P.ax(to_dev(u)))
+    o = oracle.box_mesh(wl.nx, wl.nx, wl.nx, wl.lx, wl.eps)
+    xi, wq = oracle.gll(wl.lx)
+    D = oracle.deriv_matrix(xi)
+    npe = wl.lx ** 3
+    rng = np.random.default_rng(7)
+    els = np.concatenate([[0, P.msh.nelv - 1], rng.choice(P.msh.nelv, 254, replace=False)])
+    idx = (els[:, None] * npe + np.arange(npe)[None, :]).reshape(-1)
+    G, B, _ = oracle.geometry(wl.lx, D, wq, o["x"][idx], o["y"][idx], o["z"][idx])
+    wr = oracle.ax_helm(wl.lx, D, G, B, u[idx], 1.0, 0.0)
+    assert rel_inf(w[idx], wr) <= 1e-12
+    # property at full size: constants are in the null space of every element
+    ones = torch.ones(P.n, dtype=torch.float64, device=DEV)
+    w1 = P.ax(ones)
+    assert float(w1.abs().max()) <= 1e-12 * float(torch.from_numpy(np.abs(G).max(axis=1)).max())
+    del P
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ gather-scatter, mask, Jacobi
+@pytest.mark.parametrize("nx,lx", [(4, 6), (3, 8), (2, 12), (1, 4), (5, 3)])
+def test_gs_mask_bit_exact(nx, lx):
+    say(f"[gs] nx={nx} lx={lx}")
+    P, O = pair(nx, lx)
+    u = workloads.uniform(P.n, 3)
+    g = host(P.gs.op(to_dev(u)))
+    np.testing.assert_array_equal(g, O.gs.op(u))
+    U = np.concatenate([workloads.uniform(P.n, s) for s in (3, 4, 5)])
+    G3 = host(P.gs.op(to_dev(U), nfields=3)).reshape(3, -1)
+    for f, s in enumerate((3, 4, 5)):
+        np.testing.assert_array_equal(G3[f], O.gs.op(workloads.uniform(P.n, s)))
+    # FP32: exact on integer-valued data
+    ui = np.floor(workloads.uniform(P.n, 9) * 1000)
+    g32 = host(P.gs.op(to_dev(ui, torch.float32)))
+    np.testing.assert_array_equal(g32, O.gs.op(ui))
+    m = host(sem.mask(to_dev(u), P.msh))
+    np.testing.assert_array_equal(m, np.where(O.dirichlet == 1, 0.0, u))
+
+
+@pytest.mark.parametrize("nx,lx", [(4, 6), (3, 8), (2, 12)])
+def test_jacobi_inverse(nx, lx):
+    say(f"[jacobi] nx={nx} lx={lx}")
+    P, O = pair(nx, lx)
+    h1v = np.exp(0.5 * workloads.uniform(P.n, 5))
+    P.coef.set_helmholtz(to_dev(h1v), 3.0)
+    O.set_coef(h1v, 3.0)
+    d = host(sem.jacobi_inverse(P.coef, P.msh, P.Xh, P.gs))
+    assert rel_inf(d, O.dinv) <= 1e-12
+    assert np.all(d[O.dirichlet == 1] == 0.0)
+    P.coef.set_helmholtz(1.0, 0.0)
+
+
+def test_empty_mesh_calls_are_noops():
+    say("[empty]")
+    Xh = sem.Space(5)
+    msh = sem.Mesh(0, 5, np.zeros(0, np.int64), None)
+    gs = sem.GS(msh)
+    coef = sem.Coef(Xh, msh, xyz=torch.zeros(0, dtype=torch.float64, device=DEV))
+    e = torch.zeros(0, dtype=torch.float64, device=DEV)
+    sem.ax_helm(e, e.clone(), coef, msh, Xh)
+    gs.op(e)
+    sem.mask(e, msh)
+    torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------ solvers
+def test_pcg_config1_fixed_50_iterations():
+    wl = workloads.WORKLOADS["poisson_4x4x4_lx6"]
+    say("[pcg config1]")
+    P, O = pair(wl.nx, wl.lx, wl.eps)
+    P.coef.set_helmholtz(1.0, 0.0)
+    O.set_coef(1.0, 0.0)
+    f = workloads.sine_source(O.x, O.y, O.z)
+    xo, io = O.pcg(O.assemble_rhs(O.B * f), rtol=0.0, max_iter=wl.iters)
+    _, B = P.coef.export()
+    xyz = host(P.xyz).reshape(3, -1)
+    fl = to_dev(workloads.sine_source(xyz[0], xyz[1], xyz[2])) * B
+    b = P.assemble(fl)
+    x, info = P.solve(b, rtol=0.0, max_iter=wl.iters, check_every=10)
+    assert info[0]["iters"] == io["iters"] == 50
+    assert rel_inf(host(x), xo) <= 1e-12
+    assert np.abs(host(x) - workloads.sine_exact(O.x, O.y, O.z)).max() < 1e-7
+
+
+@pytest.mark.parametrize("nx,lx,h2", [(6, 8, 0.0), (3, 12, 100.0), (5, 5, 0.0)])
+def test_pcg_to_tolerance(nx, lx, h2):
+    say(f"[pcg rtol] nx={nx} lx={lx} h2={h2}")
+    P, O = pair(nx, lx)
+    P.coef.set_helmholtz(1.0, h2)
+    O.set_coef(1.0, h2)
+    bl = workloads.uniform(P.n, workloads.SEED_RHS)
+    bo = O.assemble_rhs(bl)
+    b = P.assemble(to_dev(bl))
+    np.testing.assert_array_equal(host(b), bo)
+    xo, io = O.pcg(bo, rtol=1e-10)
+    x, info = P.solve(b, rtol=1e-10, check_every=20)
+    it, ito = info[0]["iters"], io["iters"]
+    assert abs(it - ito) <= max(2, math.ceil(0.01 * ito)), (it, ito)
+    xh = host(x)
+    assert rel_inf(xh, xo) <= 1e-8
+    tr = O.true_rel_res(xh, bo)
+    assert tr <= 1.05e-10, tr
+    assert abs(info[0]["true_rel_res"] - tr) <= 1e-3 * tr + 1e-15
+    P.coef.set_helmholtz(1.0, 0.0)
+
+
+def test_pcg_three_fields_and_initial_guess():
+    say("[pcg nf=3]")
+    P, O = pair(3, 8)
+    P.coef.set_helmholtz(1.0 / 5000.0, 1.0 / 5e-4)
+    O.set_coef(1.0 / 5000.0, 1.0 / 5e-4)
+    bls = [workloads.uniform(P.n, s) for s in workloads.SEED_RHS_FIELDS]
+    b = P.assemble(to_dev(np.concatenate(bls)), nfields=3)
+    x, info = P.solve(b, nfields=3, rtol=1e-10)
+    X = host(x).reshape(3, -1)
+    for f in range(3):
+        xo, io = O.pcg(O.assemble_rhs(bls[f]), rtol=1e-10)
+        assert abs(info[f]["iters"] - io["iters"]) <= 2
+        assert rel_inf(X[f], xo) <= 1e-8
+    # restart from the converged solution: zero iterations
+    x2 = x.clone()
+    info2 = sem.pcg_solve(x2, b, P.coef, P.msh, P.Xh, P.gs, nfields=3, rtol=1e-9, use_x0=True)
+    assert all(d["iters"] == 0 for d in info2)
+    P.coef.set_helmholtz(1.0, 0.0)
+
+
+@pytest.mark.parametrize("nx,lx", [(6, 8), (3, 12)])
+def test_mixed_precision_solve(nx, lx):
+    say(f"[mixed] nx={nx} lx={lx}")
+    P, O = pair(nx, lx)
+    P.coef.set_helmholtz(1.0, 0.0)
+    O.set_coef(1.0, 0.0)
+    bl = workloads.uniform(P.n, workloads.SEED_RHS)
+    bo = O.assemble_rhs(bl)
+    b = P.assemble(to_dev(bl))
+    x, info = P.solve(b, rtol=1e-10, mixed=True, inner_rtol=1e-4, inner_max_iter=3000)
+    xh = host(x)
+    tr = O.true_rel_res(xh, bo)
+    assert tr <= 1.05e-10, tr
+    xo, _ = O.pcg(bo, rtol=1e-12)
+    say(f"   outer={info[0]['iters']} inner={info[0]['inner_iters']} err={rel_inf(xh, xo):.2e}")
+    assert rel_inf(xh, xo) <= 1e-7
+
+
+def test_solver_error_paths():
+    say("[errors]")
+    P, O = pair(3, 8)
+    P.coef.set_helmholtz(1.0, 0.0)
+    b = P.assemble(to_dev(workloads.uniform(P.n, 1)))
+    x = torch.zeros_like(b)
+    with pytest.raises(sem.SemError, match="NOT_CONVERGED"):
+        sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-12, max_iter=3)
+    info = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-12, max_iter=3, raise_on_fail=False)
+    assert info[0]["iters"] == 3 and info[0]["converged"] == 0
+    interior = int(np.flatnonzero(O.dirichlet == 0)[0])
+    wall = int(np.flatnonzero(O.dirichlet == 1)[0])
+    for idx in (interior, wall):                                    # non-finite input anywhere
+        for mixed in (False, True):
+            bn = b.clone()
+            bn[idx] = float("nan")
+            with pytest.raises(sem.SemError, match="BREAKDOWN"):
+                sem.pcg_solve(torch.zeros_like(b), bn, P.coef, P.msh, P.Xh, P.gs, rtol=1e-10, max_iter=50,
+                              mixed=mixed)
+    with pytest.raises(sem.SemError, match="INVALID"):
+        sem.ax_helm(b, b, P.coef, P.msh, P.Xh)                     # aliasing
+    with pytest.raises(sem.SemError, match="INVALID"):
+        sem.pcg_solve(b, b, P.coef, P.msh, P.Xh, P.gs)              # x aliases b
+    Q = sem.BoxProblem.build(2, 5, 0.05, fp32=False)
+    u32 = torch.zeros(Q.n, dtype=torch.float32, device=DEV)
+    with pytest.raises(sem.SemError, match="SEM_COEF_F32"):
+        sem.ax_helm(torch.zeros_like(u32), u32, Q.coef, Q.msh, Q.Xh)
+    with pytest.raises(sem.SemError, match="INVALID"):
+        sem.ax_helm(torch.zeros(Q.n, dtype=torch.float64, device=DEV),
+                    torch.zeros(Q.n, dtype=torch.float64, device=DEV), P.coef, Q.msh, Q.Xh)  # wrong mesh
+    with pytest.raises(sem.SemError, match="Jacobian"):
+        Xh = sem.Space(4)
+        m = sem.box_mesh(2, 2, 2, 4, 0.0)
+        xyz = m["xyz"].copy()
+        xyz[0] = -xyz[0]                                             # mirrored: J < 0
+        sem.Coef(Xh, sem.Mesh(8, 4, m["glb"], m["dirichlet"]), xyz=to_dev(xyz))
+    assert torch.isfinite(x).all()
+
+
+# ------------------------------------------------------------------ adjoint and gradient
+@pytest.mark.parametrize("nx,lx", [(3, 8), (2, 12), (4, 6)])
+def test_adjoint_fp64(nx, lx):
+    say(f"[adjoint] nx={nx} lx={lx}")
+    P, O = pair(nx, lx)
+    u = workloads.uniform(P.n, 0)
+    v = workloads.uniform(P.n, 1)
+    g = host(P.adjoint(to_dev(u), to_dev(v)))
+    gr = O.adjoint(u, v)
+    assert rel_inf(g, gr) <= 1e-12
+    g32 = host(P.adjoint(to_dev(u, torch.float32), to_dev(v, torch.float32)))
+    assert rel_inf(g32, gr) <= 5e-6
+
+
+def _oracle_grad(O, h1, h2, b, ut, rtol=1e-13):
+    O.set_coef(h1, h2)
+    u, i1 = O.pcg(b, rtol=rtol)
+    d = u - ut
+    L = 0.5 * O.dot(d, d)
+    lam, i2 = O.pcg(np.where(O.dirichlet == 1, 0.0, d), rtol=rtol)
+    return L, -O.adjoint(u, lam), u
+
+
+def test_gradient_helmholtz_grf():
+    """Variable-coefficient Helmholtz (h1 = exp(GRF), h2 = 1/dt = 1000): dL/dh1 from the
+    adjoint solve + h1-adjoint kernel against the oracle's gradient and against central
+    finite differences (eps = 1e-6) along a random direction."""
+    say("[gradient]")
+    nx, lx, h2 = 4, 8, 1000.0
+    P, O = pair(nx, lx)
+    field, field2 = workloads.grf(workloads.SEED_GRF), workloads.grf(workloads.SEED_GRF_TARGET)
+    xyz = host(P.xyz).reshape(3, -1)
+    h1_np = np.exp(field(xyz[0], xyz[1], xyz[2]))
+    h1t_np = h1_np * np.exp(0.1 * field2(xyz[0], xyz[1], xyz[2]))
+    _, B = P.coef.export()
+    src = to_dev(workloads.sine_source(xyz[0], xyz[1], xyz[2])) * B
+    b = P.assemble(src)
+    # target from the perturbed coefficient
+    P.coef.set_helmholtz(to_dev(h1t_np), h2)
+    ut, _ = P.solve(b, rtol=1e-13)
+    mult = torch.from_numpy(P.gs.maps()[3].astype(np.float64)).to(DEV)
+
+    def loss(h1):
+        u = HelmholtzSolve.apply(h1, b, P, h2, 1e-13)
+        return 0.5 * torch.sum((u - ut) ** 2 / mult)
+
+    h1 = to_dev(h1_np).requires_grad_(True)
+    L = loss(h1)
+    L.backward()
+    grad = host(h1.grad)
+    # oracle gradient from its own coordinates, geometry and solves
+    oh1 = np.exp(field(O.x, O.y, O.z))
+    oh1t = oh1 * np.exp(0.1 * field2(O.x, O.y, O.z))
+    ob = O.assemble_rhs(O.B * workloads.sine_source(O.x, O.y, O.z))
+    O.set_coef(oh1t, h2)
+    out, _ = O.pcg(ob, rtol=1e-13)
+    Lo, go, _ = _oracle_grad(O, oh1, h2, ob, out)
+    assert abs(float(L) - Lo) <= 1e-9 * abs(Lo)
+    assert rel_inf(grad, go) <= 1e-8, rel_inf(grad, go)
+    # central differences along a random direction
+    dh = to_dev(workloads.uniform(P.n, 13)) * h1.detach()
+    eps = 1e-6
+    with torch.no_grad():
+        fp = float(loss(h1.detach() + eps * dh))
+        fm = float(loss(h1.detach() - eps * dh))
+    fd = (fp - fm) / (2 * eps)
+    an = float(torch.dot(h1.grad, dh))
+    say(f"   fd={fd:.10e} adj={an:.10e}")
+    assert abs(fd - an) <= 1e-6 * abs(an)
+    P.coef.set_helmholtz(1.0, 0.0)
