@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--reps", type=int, default=20, help="ax_helm launches per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: one plain device copy of 2^27 doubles (reference "
+                         "for counter scaling), --reps ax_helm launches, one gs_op and 20 PCG iterations")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the multi-GPU path "
@@ -96,6 +99,35 @@ def main():
     log(f"setup {time.time() - t0:.1f}s, n_local={P.n}")
 
     stream = torch.cuda.current_stream()
+
+    # copy bandwidth beta (the paper's STREAM-type beta): device-to-device copy of 1 GiB
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    beta_copy = 2 * src.numel() * 8 * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    log(f"device copy bandwidth {beta_copy:.0f} GB/s")
+    del src, dst
+
+    if a.profile:
+        sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
+        for _ in range(a.reps):
+            sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
+        P.gs.op(w)
+        x.zero_()
+        sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-30, max_iter=20, check_every=20,
+                      raise_on_fail=False)
+        x.zero_()
+        sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-10, mixed=True, inner_rtol=1e-4,
+                      inner_max_iter=20, max_iter=1, check_every=20, raise_on_fail=False)
+        torch.cuda.synchronize()
+        log("profile pass done")
+        return
 
     def step(record):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
@@ -167,6 +199,8 @@ def main():
         "config": {"workload": wl.name, "elements": wl.nelv, "lx": wl.lx, "n_local": P.n,
                    "n_unique": wl.n_unique, "deformation": wl.eps, "h1": 1.0, "h2": 0.0,
                    "rtol": wl.rtol, "ax_launches_per_step": a.reps},
+        "beta_copy_GBs": round(beta_copy, 1),
+        "ax_frac_of_copy_beta": round(achieved / beta_copy, 4),
         "ax_us": round(ax_s * 1e6, 2),
         "gs_us": round(float(np.mean(rec["gs_ms"])) * 1e3, 2),
         "pcg_fp64_solve_s": round(float(np.median(rec["pcg64_s"])), 4),

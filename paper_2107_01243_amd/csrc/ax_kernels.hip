@@ -10,9 +10,9 @@
 //   r-pencil: the lx points (i = 0..lx-1, j = a, k = b)   (contiguous in HBM)
 //   s-pencil: the lx points (i = a, j = 0..lx-1, k = b)
 //   t-pencil: the lx points (i = a, j = b, k = 0..lx-1)
-// Each 1-D derivative is then a register-only lx x lx matrix-vector product whose
-// D entries are wave-uniform (D travels in the kernel-argument segment and is read
-// through scalar loads).  LDS is used only to transpose pencils; every LDS row has
+// Each 1-D derivative is then a register-only product with D in its even-odd form
+// (half the FMAs of the dense lx x lx product); its entries are wave-uniform (they
+// travel in the kernel-argument segment and are read through scalar loads).  LDS is used only to transpose pencils; every LDS row has
 // stride lx+1 so that r-pencil and s-pencil accesses avoid bank conflicts.
 // HBM traffic is the algorithmic minimum: each lane reads and writes whole
 // r-pencils (lx contiguous values), i.e. coalesced element-major streams.
@@ -68,36 +68,74 @@ struct Lds {
 template <int LX>
 __device__ __forceinline__ int lidx(int i, int j, int k) { return i + (LX + 1) * (j + LX * k); }
 
-// out[m] = sum_l D[m][l] in[l]   (derivative along the pencil)
+// out = D in   (derivative along the pencil), even-odd form
 template <int LX, typename T>
-__device__ __forceinline__ void dmul(const DMat<LX, T> &D, const T (&in)[LX], T (&out)[LX])
+__device__ __forceinline__ void dmul(const DEo<LX, T> &D, const T (&in)[LX], T (&out)[LX])
 {
+    constexpr int H = LX / 2, N = LX - 1;
+    T e[H > 0 ? H : 1], o[H > 0 ? H : 1];
 #pragma unroll
-    for (int m = 0; m < LX; ++m) {
-        T s = D.d[m * LX] * in[0];
+    for (int l = 0; l < H; ++l) {
+        e[l] = in[l] + in[N - l];
+        o[l] = in[l] - in[N - l];
+    }
 #pragma unroll
-        for (int l = 1; l < LX; ++l) s = fma(D.d[m * LX + l], in[l], s);
-        out[m] = s;
+    for (int m = 0; m < H; ++m) {
+        T se = D.S[m * H] * e[0];
+        T ao = D.A[m * H] * o[0];
+#pragma unroll
+        for (int l = 1; l < H; ++l) {
+            se = fma(D.S[m * H + l], e[l], se);
+            ao = fma(D.A[m * H + l], o[l], ao);
+        }
+        if constexpr (LX % 2 == 1) se = fma(D.cm[m], in[H], se);
+        out[m] = ao + se;
+        out[N - m] = ao - se;
+    }
+    if constexpr (LX % 2 == 1) {
+        T c = T(0);
+#pragma unroll
+        for (int l = 0; l < H; ++l) c = fma(D.rm[l], o[l], c);
+        out[H] = c;
     }
 }
 
-// out[m] = sum_l D[l][m] in[l]   (transposed derivative along the pencil)
+// out = D^T in   (transposed derivative along the pencil), even-odd form
 template <int LX, typename T>
-__device__ __forceinline__ void dtmul(const DMat<LX, T> &D, const T (&in)[LX], T (&out)[LX])
+__device__ __forceinline__ void dtmul(const DEo<LX, T> &D, const T (&in)[LX], T (&out)[LX])
 {
+    constexpr int H = LX / 2, N = LX - 1;
+    T e[H > 0 ? H : 1], o[H > 0 ? H : 1];
 #pragma unroll
-    for (int m = 0; m < LX; ++m) {
-        T s = D.d[m] * in[0];
+    for (int l = 0; l < H; ++l) {
+        e[l] = in[l] + in[N - l];
+        o[l] = in[l] - in[N - l];
+    }
 #pragma unroll
-        for (int l = 1; l < LX; ++l) s = fma(D.d[l * LX + m], in[l], s);
-        out[m] = s;
+    for (int m = 0; m < H; ++m) {
+        T se = D.A[m] * e[0];
+        T ao = D.S[m] * o[0];
+#pragma unroll
+        for (int l = 1; l < H; ++l) {
+            se = fma(D.A[l * H + m], e[l], se);
+            ao = fma(D.S[l * H + m], o[l], ao);
+        }
+        if constexpr (LX % 2 == 1) se = fma(D.rm[m], in[H], se);
+        out[m] = ao + se;
+        out[N - m] = ao - se;
+    }
+    if constexpr (LX % 2 == 1) {
+        T c = T(0);
+#pragma unroll
+        for (int l = 0; l < H; ++l) c = fma(D.cm[l], o[l], c);
+        out[H] = c;
     }
 }
 
 // Reference-space gradient of one field held as the lane's r-pencil `u`.
 // Returns ur, us, ut as r-pencils.  Uses both LDS buffers; ends synchronised.
 template <int LX, typename T>
-__device__ __forceinline__ void grad(const DMat<LX, T> &D, const T (&u)[LX], T *s0, T *s1,
+__device__ __forceinline__ void grad(const DEo<LX, T> &D, const T (&u)[LX], T *s0, T *s1,
                                      int a, int b, T (&ur)[LX], T (&us)[LX], T (&ut)[LX])
 {
     dmul<LX, T>(D, u, ur);
@@ -128,7 +166,7 @@ __device__ __forceinline__ void grad(const DMat<LX, T> &D, const T (&u)[LX], T *
 
 // acc = D_r^T wr + D_s^T ws + D_t^T wt for r-pencils wr, ws, wt.  Ends synchronised.
 template <int LX, typename T>
-__device__ __forceinline__ void div(const DMat<LX, T> &D, const T (&wr)[LX], const T (&ws)[LX],
+__device__ __forceinline__ void div(const DEo<LX, T> &D, const T (&wr)[LX], const T (&ws)[LX],
                                     const T (&wt)[LX], T *s0, T *s1, int a, int b, T (&acc)[LX])
 {
     dtmul<LX, T>(D, wr, acc);
@@ -195,7 +233,7 @@ __device__ __forceinline__ void apply_G(const T (&g)[6][LX], const T (&h1)[LX], 
 // ------------------------------------------------------------------ w = A_L u
 // NF fields share one read of G (and B, h1, h2).
 template <int LX, typename T, int NF>
-__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DMat<LX, T> D)
+__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
     __shared__ Lds<LX, T> lds;
@@ -253,7 +291,7 @@ __global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DMa
 //   w = A_L p,   partial_f += sum p * w   (the unassembled identity p^T A p = p_L^T A_L p_L)
 // Partials are per workgroup; a separate kernel reduces them in a fixed order.
 template <int LX, typename T, int NF>
-__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DMat<LX, T> D)
+__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
     __shared__ Lds<LX, T> lds;
@@ -340,7 +378,7 @@ __global__ __launch_bounds__((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T
 // ------------------------------------------------------------------ h1-adjoint
 // g = (D v)^T G (D u) per point.
 template <int LX, typename T>
-__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_adjoint(AdjArgs<T> A, DMat<LX, T> D)
+__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_adjoint(AdjArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
     __shared__ Lds<LX, T> lds;
@@ -476,13 +514,33 @@ sem::DMat<LX, T> make_dmat(const double *D)
     return m;
 }
 
+template <int LX, typename T>
+sem::DEo<LX, T> make_deo(const double *D)
+{
+    using E = sem::DEo<LX, T>;
+    constexpr int H = E::H, N = LX - 1;
+    E m{};
+    for (int a = 0; a < H; ++a)
+        for (int l = 0; l < H; ++l) {
+            m.S[a * H + l] = (T)(0.5 * (D[a * LX + l] + D[a * LX + (N - l)]));
+            m.A[a * H + l] = (T)(0.5 * (D[a * LX + l] - D[a * LX + (N - l)]));
+        }
+    if constexpr (LX % 2 == 1) {
+        for (int a = 0; a < H; ++a) {
+            m.cm[a] = (T)D[a * LX + H];
+            m.rm[a] = (T)D[H * LX + a];
+        }
+    }
+    return m;
+}
+
 template <typename T>
 hipError_t launch_ax(const sem::AxArgs<T> &A, const double *D, int nfields, hipStream_t st)
 {
     using S = sem::Shape<SEM_LX, T>;
     const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
     if (grid == 0) return hipSuccess;
-    const auto Dm = make_dmat<SEM_LX, T>(D);
+    const auto Dm = make_deo<SEM_LX, T>(D);
     if (nfields == 3)
         hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 3>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
     else
@@ -496,7 +554,7 @@ hipError_t launch_cg(const sem::CgMatvecArgs<T> &A, const double *D, int nfields
     using S = sem::Shape<SEM_LX, T>;
     const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
     if (grid == 0) return hipSuccess;
-    const auto Dm = make_dmat<SEM_LX, T>(D);
+    const auto Dm = make_deo<SEM_LX, T>(D);
     if (nfields == 3)
         hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
     else
@@ -511,7 +569,7 @@ hipError_t launch_adj(const sem::AdjArgs<T> &A, const double *D, hipStream_t st)
     const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL((sem::k_ax_adjoint<SEM_LX, T>), dim3(grid), dim3(S::NT), 0, st, A,
-                       make_dmat<SEM_LX, T>(D));
+                       make_deo<SEM_LX, T>(D));
     return hipGetLastError();
 }
 }  // namespace

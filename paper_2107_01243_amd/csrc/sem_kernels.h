@@ -13,6 +13,26 @@ struct DMat {
     T d[LX * LX];
 };
 
+// Even-odd form of D used by the operator kernels.  GLL points are symmetric, so
+// D is centro-antisymmetric: D[N-m][N-l] = -D[m][l] (N = LX-1).  With H = LX/2,
+// e_l = u_l + u_{N-l}, o_l = u_l - u_{N-l} (l < H) and c = u_H (odd LX only):
+//   (D u)_m     =  sum_l S[m][l] e_l + cm[m] c + sum_l A[m][l] o_l
+//   (D u)_{N-m} = -sum_l S[m][l] e_l - cm[m] c + sum_l A[m][l] o_l      (m < H)
+//   (D u)_H     =  sum_l rm[l] o_l                                      (odd LX)
+// with S = (D[m][l] + D[m][N-l])/2, A = (D[m][l] - D[m][N-l])/2, cm[m] = D[m][H],
+// rm[l] = D[H][l].  D^T has the same structure with S^T -> A and A^T -> S, so one
+// set of constants serves both products (half the FMAs of the dense product, and
+// half the wave-uniform constants).
+template <int LX, typename T>
+struct DEo {
+    static constexpr int H = LX / 2;
+    static constexpr int HM = (LX % 2) ? H : 1;
+    T S[H * H];
+    T A[H * H];
+    T cm[HM];
+    T rm[HM];
+};
+
 template <int LX>
 struct WVec {
     double w[LX];

@@ -265,6 +265,29 @@ def test_mixed_precision_solve(nx, lx):
     assert rel_inf(xh, xo) <= 1e-7
 
 
+def test_mixed_three_fields_lx12():
+    """Three velocity Helmholtz solves in one batch (h1 = 1/Re, Re = 5000; h2 = 1/dt,
+    dt = 5e-4), FP32 operator inside FP64 flexible CG, each field checked by the oracle's
+    own FP64 operator."""
+    say("[mixed nf=3 lx=12]")
+    P, O = pair(3, 12)
+    h1, h2 = 1.0 / 5000.0, 1.0 / 5e-4
+    P.coef.set_helmholtz(h1, h2)
+    O.set_coef(h1, h2)
+    bls = [workloads.uniform(P.n, s) for s in workloads.SEED_RHS_FIELDS]
+    b = P.assemble(to_dev(np.concatenate(bls)), nfields=3)
+    x, info = P.solve(b, nfields=3, rtol=1e-10, mixed=True, inner_rtol=1e-4, inner_max_iter=2000)
+    X = host(x).reshape(3, -1)
+    for f in range(3):
+        bo = O.assemble_rhs(bls[f])
+        tr = O.true_rel_res(X[f], bo)
+        assert tr <= 1.05e-10, (f, tr)
+        assert abs(info[f]["true_rel_res"] - tr) <= 1e-2 * tr + 1e-13   # rounding floor of b - Ax
+        xo, _ = O.pcg(bo, rtol=1e-12)
+        assert rel_inf(X[f], xo) <= 1e-8
+    P.coef.set_helmholtz(1.0, 0.0)
+
+
 def test_solver_error_paths():
     say("[errors]")
     P, O = pair(3, 8)
