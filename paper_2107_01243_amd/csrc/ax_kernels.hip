@@ -27,6 +27,23 @@
 #ifndef SEM_LX
 #error "compile with -DSEM_LX=<lx>"
 #endif
+#ifndef SEM_WAVE_SYNC
+#define SEM_WAVE_SYNC 1
+#endif
+#ifndef SEM_G_LATE
+#define SEM_G_LATE 0
+#endif
+#ifndef SEM_MIN_WAVES
+#define SEM_MIN_WAVES 0
+#endif
+#ifndef SEM_NT_G
+#define SEM_NT_G 0
+#endif
+#if SEM_MIN_WAVES > 0
+#define SEM_BOUNDS(NT) __launch_bounds__((NT), SEM_MIN_WAVES)
+#else
+#define SEM_BOUNDS(NT) __launch_bounds__((NT))
+#endif
 
 namespace sem {
 
@@ -63,6 +80,26 @@ template <int LX, typename T>
 struct Lds {
     T buf[2][Shape<LX, T>::EPB][Shape<LX, T>::ESZ];
 };
+
+// Synchronise the lanes that share one element's LDS buffers.  When whole elements
+// fit inside one wave64 (lx*lx divides 64, e.g. lx = 8: one element per wave) no
+// other wave touches those buffers, and LDS operations of one wave complete in
+// order, so a wave-level barrier (a compiler fence, no s_barrier) suffices.
+template <int LX>
+__device__ __forceinline__ void esync()
+{
+#if SEM_WAVE_SYNC
+    if constexpr (64 % (LX * LX) == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+#else
+    __syncthreads();
+#endif
+}
 
 // LDS index of point (i, j, k) inside one element buffer.
 template <int LX>
@@ -141,7 +178,7 @@ __device__ __forceinline__ void grad(const DEo<LX, T> &D, const T (&u)[LX], T *s
     dmul<LX, T>(D, u, ur);
 #pragma unroll
     for (int i = 0; i < LX; ++i) s0[lidx<LX>(i, a, b)] = u[i];
-    __syncthreads();
+    esync<LX>();
     T v[LX], q[LX];
 #pragma unroll
     for (int l = 0; l < LX; ++l) v[l] = s0[lidx<LX>(a, l, b)];   // s-pencil (i=a, k=b)
@@ -152,16 +189,16 @@ __device__ __forceinline__ void grad(const DEo<LX, T> &D, const T (&u)[LX], T *s
     dmul<LX, T>(D, v2, q2);
 #pragma unroll
     for (int m = 0; m < LX; ++m) s1[lidx<LX>(a, b, m)] = q2[m];
-    __syncthreads();
+    esync<LX>();
 #pragma unroll
     for (int m = 0; m < LX; ++m) s0[lidx<LX>(a, m, b)] = q[m];
-    __syncthreads();
+    esync<LX>();
 #pragma unroll
     for (int i = 0; i < LX; ++i) {
         us[i] = s0[lidx<LX>(i, a, b)];
         ut[i] = s1[lidx<LX>(i, a, b)];
     }
-    __syncthreads();
+    esync<LX>();
 }
 
 // acc = D_r^T wr + D_s^T ws + D_t^T wt for r-pencils wr, ws, wt.  Ends synchronised.
@@ -175,7 +212,7 @@ __device__ __forceinline__ void div(const DEo<LX, T> &D, const T (&wr)[LX], cons
         s0[lidx<LX>(i, a, b)] = ws[i];
         s1[lidx<LX>(i, a, b)] = wt[i];
     }
-    __syncthreads();
+    esync<LX>();
     T v[LX], q[LX], v2[LX], q2[LX];
 #pragma unroll
     for (int l = 0; l < LX; ++l) v[l] = s0[lidx<LX>(a, l, b)];
@@ -183,16 +220,16 @@ __device__ __forceinline__ void div(const DEo<LX, T> &D, const T (&wr)[LX], cons
     for (int l = 0; l < LX; ++l) v2[l] = s1[lidx<LX>(a, b, l)];
     dtmul<LX, T>(D, v, q);
     dtmul<LX, T>(D, v2, q2);
-    __syncthreads();
+    esync<LX>();
 #pragma unroll
     for (int m = 0; m < LX; ++m) {
         s0[lidx<LX>(a, m, b)] = q[m];
         s1[lidx<LX>(a, b, m)] = q2[m];
     }
-    __syncthreads();
+    esync<LX>();
 #pragma unroll
     for (int i = 0; i < LX; ++i) acc[i] += s0[lidx<LX>(i, a, b)] + s1[lidx<LX>(i, a, b)];
-    __syncthreads();
+    esync<LX>();
 }
 
 template <int LX, typename T>
@@ -205,6 +242,24 @@ __device__ __forceinline__ void load_row(T (&r)[LX], const T *__restrict__ p, bo
 #pragma unroll
         for (int i = 0; i < LX; ++i) r[i] = T(0);
     }
+}
+
+// Geometric-factor rows are read exactly once per application: optionally as
+// non-temporal loads.
+template <int LX, typename T>
+__device__ __forceinline__ void load_g(T (&r)[LX], const T *__restrict__ p, bool act)
+{
+#if SEM_NT_G
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < LX; ++i) r[i] = __builtin_nontemporal_load(p + i);
+    } else {
+#pragma unroll
+        for (int i = 0; i < LX; ++i) r[i] = T(0);
+    }
+#else
+    load_row<LX, T>(r, p, act);
+#endif
 }
 
 template <int LX, typename T>
@@ -233,7 +288,7 @@ __device__ __forceinline__ void apply_G(const T (&g)[6][LX], const T (&h1)[LX], 
 // ------------------------------------------------------------------ w = A_L u
 // NF fields share one read of G (and B, h1, h2).
 template <int LX, typename T, int NF>
-__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo<LX, T> D)
+__global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
     __shared__ Lds<LX, T> lds;
@@ -247,8 +302,10 @@ __global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo
     T *s0 = lds.buf[0][slot], *s1 = lds.buf[1][slot];
 
     T g[6][LX];
+#if !SEM_G_LATE
 #pragma unroll
-    for (int f = 0; f < 6; ++f) load_row<LX, T>(g[f], A.G + f * A.n + row, act);
+    for (int f = 0; f < 6; ++f) load_g<LX, T>(g[f], A.G + goff(f, e, (int64_t)LX * t, (int64_t)(LX * LX * LX), A.n), act);
+#endif
     T h1[LX], h2b[LX];
     if (A.h1) load_row<LX, T>(h1, A.h1 + row, act);
     else {
@@ -274,6 +331,12 @@ __global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo
         load_row<LX, T>(u, A.u + f * A.n + row, act);
         T ur[LX], us[LX], ut[LX];
         grad<LX, T>(D, u, s0, s1, a, b, ur, us, ut);
+#if SEM_G_LATE
+        if (f == 0) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) load_g<LX, T>(g[q], A.G + goff(q, e, (int64_t)LX * t, (int64_t)(LX * LX * LX), A.n), act);
+        }
+#endif
         apply_G<LX, T>(g, h1, ur, us, ut);
         T w[LX];
         div<LX, T>(D, ur, us, ut, s0, s1, a, b, w);
@@ -291,7 +354,7 @@ __global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo
 //   w = A_L p,   partial_f += sum p * w   (the unassembled identity p^T A p = p_L^T A_L p_L)
 // Partials are per workgroup; a separate kernel reduces them in a fixed order.
 template <int LX, typename T, int NF>
-__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DEo<LX, T> D)
+__global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
     __shared__ Lds<LX, T> lds;
@@ -307,7 +370,7 @@ __global__ __launch_bounds__((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T
 
     T g[6][LX];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) load_row<LX, T>(g[f], A.G + f * A.n + row, act);
+    for (int f = 0; f < 6; ++f) load_g<LX, T>(g[f], A.G + goff(f, e, (int64_t)LX * t, (int64_t)(LX * LX * LX), A.n), act);
     T h1[LX], h2b[LX];
     if (A.h1) load_row<LX, T>(h1, A.h1 + row, act);
     else {
@@ -378,7 +441,7 @@ __global__ __launch_bounds__((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T
 // ------------------------------------------------------------------ h1-adjoint
 // g = (D v)^T G (D u) per point.
 template <int LX, typename T>
-__global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_adjoint(AdjArgs<T> A, DEo<LX, T> D)
+__global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_adjoint(AdjArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
     __shared__ Lds<LX, T> lds;
@@ -396,7 +459,7 @@ __global__ __launch_bounds__((Shape<LX, T>::NT)) void k_ax_adjoint(AdjArgs<T> A,
     load_row<LX, T>(v, A.v + row, act);
     T g[6][LX];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) load_row<LX, T>(g[f], A.G + f * A.n + row, act);
+    for (int f = 0; f < 6; ++f) load_g<LX, T>(g[f], A.G + goff(f, e, (int64_t)LX * t, (int64_t)(LX * LX * LX), A.n), act);
     T ur[LX], us[LX], ut[LX], vr[LX], vs[LX], vt[LX];
     grad<LX, T>(D, u, s0, s1, a, b, ur, us, ut);
     grad<LX, T>(D, v, s0, s1, a, b, vr, vs, vt);
@@ -456,7 +519,7 @@ __global__ __launch_bounds__(256) void k_geometry(GeomArgs A, DMat<LX, double> D
     const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
     for (int f = 0; f < 6; ++f) {
         const double d = C[0][ia[f]] * C[0][ib[f]] + C[1][ia[f]] * C[1][ib[f]] + C[2][ia[f]] * C[2][ib[f]];
-        A.G[f * A.n + p] = s * d;
+        A.G[goff(f, e, q, NPE, A.n)] = s * d;
     }
     A.B[p] = rho * J;
     if (!(J > 0.0)) atomicAdd(A.nbad, 1u);
@@ -485,15 +548,15 @@ __global__ __launch_bounds__(256) void k_diag(DiagArgs A, DMat<LX, double> D)
         const double cs = A.h1 ? A.h1[ps] : A.h1s;
         const double ct = A.h1 ? A.h1[pt] : A.h1s;
         const double dri = D.d[l * LX + i], dsj = D.d[l * LX + j], dtk = D.d[l * LX + k];
-        s += dri * dri * cr * G[pr];
-        s += dsj * dsj * cs * G[n + ps];
-        s += dtk * dtk * ct * G[2 * n + pt];
+        s += dri * dri * cr * G[goff(0, e, pr - b0, NPE, n)];
+        s += dsj * dsj * cs * G[goff(1, e, ps - b0, NPE, n)];
+        s += dtk * dtk * ct * G[goff(2, e, pt - b0, NPE, n)];
     }
     const double c = A.h1 ? A.h1[p] : A.h1s;
     const double di = D.d[i * LX + i], dj = D.d[j * LX + j], dk = D.d[k * LX + k];
-    s += 2.0 * di * dj * c * G[3 * n + p];
-    s += 2.0 * di * dk * c * G[4 * n + p];
-    s += 2.0 * dj * dk * c * G[5 * n + p];
+    s += 2.0 * di * dj * c * G[goff(3, e, q, NPE, n)];
+    s += 2.0 * di * dk * c * G[goff(4, e, q, NPE, n)];
+    s += 2.0 * dj * dk * c * G[goff(5, e, q, NPE, n)];
     const double c2 = A.h2 ? A.h2[p] : A.h2s;
     if (c2 != 0.0) s += c2 * A.B[p];
     A.d[p] = s;

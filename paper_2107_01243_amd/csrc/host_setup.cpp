@@ -176,6 +176,7 @@ bool build_gs_maps(int64_t n, const int64_t *glb, const uint8_t *dir, GsMaps &m,
     const int64_t ng = (int64_t)gid.size();
     m.n_unique = ng;
     m.blk_ptr.push_back(0);
+    m.big_ptr.push_back(0);
     for (int64_t g = 0; g < ng; ++g) {
         const int64_t lo = start[g], hi = start[g + 1], c = hi - lo;
         if (c > 255) { msg = "more than 255 copies of one global id"; return false; }
@@ -188,6 +189,19 @@ bool build_gs_maps(int64_t n, const int64_t *glb, const uint8_t *dir, GsMaps &m,
         }
         m.owner[order[lo]] = 1;
         for (int64_t q = lo; q < hi; ++q) m.mult[order[q]] = (uint8_t)c;
+        if (c >= 2 && c <= 64) {
+            const int64_t used = (int64_t)m.ent_idx.size() % 64;
+            if (used + c > 64)
+                for (int64_t q = used; q < 64; ++q) { m.ent_idx.push_back(-1); m.ent_meta.push_back(0); }
+            for (int64_t q = lo; q < hi; ++q) {
+                m.ent_idx.push_back(order[q]);
+                m.ent_meta.push_back((uint16_t)((q - lo) | (c << 8)));
+            }
+            m.max_group = std::max<int>(m.max_group, (int)c);
+        } else if (c > 64) {
+            for (int64_t q = lo; q < hi; ++q) m.big_idx.push_back(order[q]);
+            m.big_ptr.push_back((int64_t)m.big_idx.size());
+        }
         if (c == 2) {
             m.pairs.push_back(order[lo]);
             m.pairs.push_back(order[lo + 1]);
@@ -197,6 +211,31 @@ bool build_gs_maps(int64_t n, const int64_t *glb, const uint8_t *dir, GsMaps &m,
         }
     }
     return true;
+}
+
+void element_order(const GsMaps &m, std::vector<int32_t> &pairs, std::vector<int64_t> &blk_ptr,
+                   std::vector<int32_t> &blk_idx)
+{
+    const int64_t np = (int64_t)m.pairs.size() / 2;
+    std::vector<int64_t> ord(np);
+    for (int64_t q = 0; q < np; ++q) ord[q] = q;
+    std::sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return m.pairs[2 * x] < m.pairs[2 * y]; });
+    pairs.resize(2 * np);
+    for (int64_t q = 0; q < np; ++q) {
+        pairs[2 * q] = m.pairs[2 * ord[q]];
+        pairs[2 * q + 1] = m.pairs[2 * ord[q] + 1];
+    }
+    const int64_t nb = (int64_t)m.blk_ptr.size() - 1;
+    std::vector<int64_t> bo(nb);
+    for (int64_t q = 0; q < nb; ++q) bo[q] = q;
+    std::sort(bo.begin(), bo.end(), [&](int64_t x, int64_t y) { return m.blk_idx[m.blk_ptr[x]] < m.blk_idx[m.blk_ptr[y]]; });
+    blk_ptr.assign(1, 0);
+    blk_idx.clear();
+    blk_idx.reserve(m.blk_idx.size());
+    for (int64_t q = 0; q < nb; ++q) {
+        for (int64_t c = m.blk_ptr[bo[q]]; c < m.blk_ptr[bo[q] + 1]; ++c) blk_idx.push_back(m.blk_idx[c]);
+        blk_ptr.push_back((int64_t)blk_idx.size());
+    }
 }
 
 }  // namespace semh

@@ -24,6 +24,13 @@
 
 using namespace sem;
 
+#ifndef SEM_GS_ELEMENT_ORDER
+#define SEM_GS_ELEMENT_ORDER 0
+#endif
+#ifndef SEM_GS_ENTRY
+#define SEM_GS_ENTRY 1
+#endif
+
 // ------------------------------------------------------------------ launcher table
 #define SEM_LX_LIST(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
@@ -52,6 +59,7 @@ hipError_t sem_launch_fill_f64(double *, double, int64_t, hipStream_t);
 hipError_t sem_launch_fill_f32(float *, float, int64_t, hipStream_t);
 hipError_t sem_launch_cast_f32_f64(float *, const double *, double, int64_t, hipStream_t);
 hipError_t sem_launch_invert(double *, const uint8_t *, int64_t, hipStream_t);
+hipError_t sem_launch_g_relayout(double *, const double *, int64_t, int64_t, int, hipStream_t);
 hipError_t sem_launch_cg_init_f64(const CgInitArgs<double> *, unsigned, hipStream_t);
 hipError_t sem_launch_cg_init_f32(const CgInitArgs<float> *, unsigned, hipStream_t);
 hipError_t sem_launch_cg_start(const CgFinishArgs *, hipStream_t);
@@ -188,8 +196,13 @@ struct sem_gs_s {
     int64_t *d_blk_ptr = nullptr;
     int32_t *d_blk_idx = nullptr;
     uint8_t *d_owner = nullptr;
+    int32_t *d_ent_idx = nullptr;
+    uint16_t *d_ent_meta = nullptr;
+    bool entries = false;  // entry-parallel execution (groups > 64 copies via d_blk_*)
     int64_t npairs() const { return (int64_t)m.pairs.size() / 2; }
     int64_t nblocks() const { return (int64_t)m.blk_ptr.size() - 1; }
+    // work of the per-group kernel as uploaded
+    int64_t dev_npairs = 0, dev_nblocks = 0;
 };
 
 namespace {
@@ -284,14 +297,40 @@ sem_status gs_upload(sem_gs g)
     int dev;
     SEM_TRY(current_device(&dev));
     const auto &m = g->m;
-    SEM_TRY(dalloc(&g->d_pairs, m.pairs.size()));
-    SEM_TRY(dalloc(&g->d_blk_ptr, m.blk_ptr.size()));
-    SEM_TRY(dalloc(&g->d_blk_idx, m.blk_idx.size()));
+    // Device execution order.  Ascending global id (the canonical order) keeps lanes
+    // that handle consecutive ids on shared memory segments (for faces normal to the
+    // fastest grid direction, lane q's partner and lane q+1's point share a row);
+    // ordering by element instead was measured slower.  Each group's own summation
+    // order is the same either way.
+#if SEM_GS_ENTRY
+    // Entry-parallel execution: the per-group kernel keeps only groups > 64 copies.
+    const std::vector<int32_t> pairs, &blk_idx = m.big_idx;
+    const std::vector<int64_t> &blk_ptr = m.big_ptr;
+    g->entries = true;
+    SEM_TRY(dalloc(&g->d_ent_idx, m.ent_idx.size()));
+    SEM_TRY(dalloc(&g->d_ent_meta, m.ent_meta.size()));
+    if (!m.ent_idx.empty()) {
+        HIP_TRY(hipMemcpy(g->d_ent_idx, m.ent_idx.data(), m.ent_idx.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(g->d_ent_meta, m.ent_meta.data(), m.ent_meta.size() * 2, hipMemcpyHostToDevice));
+    }
+#elif SEM_GS_ELEMENT_ORDER
+    std::vector<int32_t> pairs, blk_idx;
+    std::vector<int64_t> blk_ptr;
+    semh::element_order(m, pairs, blk_ptr, blk_idx);
+#else
+    const std::vector<int32_t> &pairs = m.pairs, &blk_idx = m.blk_idx;
+    const std::vector<int64_t> &blk_ptr = m.blk_ptr;
+#endif
+    g->dev_npairs = (int64_t)pairs.size() / 2;
+    g->dev_nblocks = (int64_t)blk_ptr.size() - 1;
+    SEM_TRY(dalloc(&g->d_pairs, pairs.size()));
+    SEM_TRY(dalloc(&g->d_blk_ptr, blk_ptr.size()));
+    SEM_TRY(dalloc(&g->d_blk_idx, blk_idx.size()));
     SEM_TRY(dalloc(&g->d_owner, m.owner.size()));
-    if (!m.pairs.empty()) HIP_TRY(hipMemcpy(g->d_pairs, m.pairs.data(), m.pairs.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(g->d_blk_ptr, m.blk_ptr.data(), m.blk_ptr.size() * 8, hipMemcpyHostToDevice));
-    if (!m.blk_idx.empty())
-        HIP_TRY(hipMemcpy(g->d_blk_idx, m.blk_idx.data(), m.blk_idx.size() * 4, hipMemcpyHostToDevice));
+    if (!pairs.empty()) HIP_TRY(hipMemcpy(g->d_pairs, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_blk_ptr, blk_ptr.data(), blk_ptr.size() * 8, hipMemcpyHostToDevice));
+    if (!blk_idx.empty())
+        HIP_TRY(hipMemcpy(g->d_blk_idx, blk_idx.data(), blk_idx.size() * 4, hipMemcpyHostToDevice));
     if (!m.owner.empty()) HIP_TRY(hipMemcpy(g->d_owner, m.owner.data(), m.owner.size(), hipMemcpyHostToDevice));
     g->device = dev;
     return SEM_OK;
@@ -313,13 +352,17 @@ sem_status launch_gs(T *u, int nf, sem_gs g, const CgScalars *skip, const AlphaJ
     A.pairs = g->d_pairs;
     A.blk_ptr = g->d_blk_ptr;
     A.blk_idx = g->d_blk_idx;
-    A.npairs = g->npairs();
-    A.nblocks = g->nblocks();
+    A.npairs = g->dev_npairs;
+    A.nblocks = g->dev_nblocks;
     A.n = g->m.n;
     A.nfields = nf;
     A.skip = skip;
     A.alpha_job = job;
-    if (A.npairs + A.nblocks == 0 && job == nullptr) return SEM_OK;
+    A.ent_idx = g->d_ent_idx;
+    A.ent_meta = g->d_ent_meta;
+    A.nent = g->entries ? (int64_t)g->m.ent_idx.size() : 0;
+    A.max_group = g->m.max_group;
+    if (A.npairs + A.nblocks + A.nent == 0 && job == nullptr) return SEM_OK;
     hipError_t e;
     if constexpr (sizeof(T) == 8) e = sem_launch_gs_f64(&A, st);
     else e = sem_launch_gs_f32(&A, st);
@@ -700,6 +743,8 @@ void sem_gs_destroy(sem_gs gs)
     dfree(gs->d_blk_ptr);
     dfree(gs->d_blk_idx);
     dfree(gs->d_owner);
+    dfree(gs->d_ent_idx);
+    dfree(gs->d_ent_meta);
     delete gs;
 }
 
@@ -810,7 +855,7 @@ sem_status sem_coef_create_from_G(sem_space Xh, sem_mesh msh, const double *G6_d
     hipStream_t st = S(stream);
     hipError_t e = hipSuccess;
     if (c->n > 0) {
-        e = hipMemcpyAsync(c->G, G6_dev, sizeof(double) * 6 * c->n, hipMemcpyDeviceToDevice, st);
+        e = sem_launch_g_relayout(c->G, G6_dev, c->nelv, c->n / c->nelv, 1, st);
         if (e == hipSuccess) e = hipMemcpyAsync(c->B, B_dev, sizeof(double) * c->n, hipMemcpyDeviceToDevice, st);
     }
     if (e != hipSuccess) {
@@ -864,7 +909,7 @@ sem_status sem_coef_export(sem_coef c, double *G6_dev, double *B_dev, void *stre
 {
     if (!c) return fail(SEM_ERR_INVALID, "coef is NULL");
     SEM_TRY(check_device(c->device));
-    if (G6_dev) HIP_TRY(hipMemcpyAsync(G6_dev, c->G, sizeof(double) * 6 * c->n, hipMemcpyDeviceToDevice, S(stream)));
+    if (G6_dev && c->n > 0) HIP_TRY(sem_launch_g_relayout(G6_dev, c->G, c->nelv, c->n / c->nelv, 0, S(stream)));
     if (B_dev) HIP_TRY(hipMemcpyAsync(B_dev, c->B, sizeof(double) * c->n, hipMemcpyDeviceToDevice, S(stream)));
     return SEM_OK;
 }

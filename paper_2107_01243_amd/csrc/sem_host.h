@@ -16,6 +16,15 @@ struct GsMaps {
     std::vector<int32_t> blk_idx;  // ascending local index inside a block
     std::vector<uint8_t> mult;     // copies of each local point's global id
     std::vector<uint8_t> owner;    // 1 on the lowest local index of every global id
+    // Entry-parallel form of the same groups, ascending global id: one entry per
+    // shared local point; a group never straddles a 64-entry (wave) boundary, gaps
+    // are padding entries (index -1).  meta = position in group | (group size << 8).
+    std::vector<int32_t> ent_idx;
+    std::vector<uint16_t> ent_meta;
+    int max_group = 0;             // largest group size among the entries
+    // Groups with more than 64 copies (never in hexahedral box meshes) use CSR only.
+    std::vector<int64_t> big_ptr;
+    std::vector<int32_t> big_idx;
 };
 
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn);
@@ -23,5 +32,8 @@ void gll_space(int lx, double *xi, double *w, double *D);
 void box_mesh(int nx, int ny, int nz, int lx, double eps, const double *xi, int64_t *glb,
               uint8_t *dir, double *xyz);
 bool build_gs_maps(int64_t n, const int64_t *glb, const uint8_t *dir, GsMaps &m, std::string &msg);
+// The same groups reordered by their lowest local index (execution order on the device).
+void element_order(const GsMaps &m, std::vector<int32_t> &pairs, std::vector<int64_t> &blk_ptr,
+                   std::vector<int32_t> &blk_idx);
 
 }  // namespace semh

@@ -26,6 +26,12 @@ struct GsArgs {
     int nfields;
     const CgScalars *skip;   // optional: fields with skip[f].stop are left untouched
     const AlphaJob *alpha_job;  // optional (device pointer)
+    // entry-parallel form (used when nent > 0; pairs/blocks then hold only groups
+    // with more than 64 copies)
+    const int32_t *ent_idx;
+    const uint16_t *ent_meta;
+    int64_t nent;
+    int max_group;
 };
 
 template <typename T>

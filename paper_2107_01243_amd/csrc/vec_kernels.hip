@@ -17,20 +17,35 @@
 #include "sem_kernels.h"
 #include "vec_kernels.h"
 
+#ifndef SEM_GS_XCD
+#define SEM_GS_XCD 1
+#endif
+
 namespace sem {
 
-constexpr int VT = 256;  // lanes per workgroup of the streaming kernels
+constexpr int VT = 256;   // lanes per workgroup of the streaming kernels
+constexpr int RT = 1024;  // lanes of the single-workgroup reduction kernels
 
-// Reduce `nblk` partials per field (layout [field][nblk]) in a fixed order.
-// Runs inside one workgroup of VT lanes; returns the sum on lane 0.
+// Sum `nblk` partials in a fixed order inside one workgroup of NTH lanes: lane t
+// accumulates entries t, t+NTH, ... into four interleaved accumulators (loads in
+// flight), combines them, then a fixed binary tree in LDS.  Deterministic for a
+// given (nblk, NTH).  Returns the sum to every lane.
+template <int NTH>
 __device__ double block_sum_fixed(const double *part, int64_t nblk, double *sh)
 {
     const int tid = threadIdx.x;
-    double s = 0.0;
-    for (int64_t q = tid; q < nblk; q += VT) s += part[q];
-    sh[tid] = s;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t q = tid;
+    for (; q + 3 * NTH < nblk; q += 4 * NTH) {
+        a0 += part[q];
+        a1 += part[q + NTH];
+        a2 += part[q + 2 * NTH];
+        a3 += part[q + 3 * NTH];
+    }
+    for (; q < nblk; q += NTH) a0 += part[q];
+    sh[tid] = (a0 + a1) + (a2 + a3);
     __syncthreads();
-    for (int w = VT / 2; w > 0; w >>= 1) {
+    for (int w = NTH / 2; w > 0; w >>= 1) {
         if (tid < w) sh[tid] += sh[tid + w];
         __syncthreads();
     }
@@ -43,7 +58,16 @@ __device__ double block_sum_fixed(const double *part, int64_t nblk, double *sh)
 template <typename T>
 __global__ __launch_bounds__(VT) void k_gs(GsArgs<T> A)
 {
-    const int64_t tid = (int64_t)blockIdx.x * VT + threadIdx.x;
+    // Workgroups are dealt to the 8 XCDs round-robin by the hardware.  Map them so
+    // that XCD x processes one contiguous slice of the group list (which is ordered
+    // by element), so each XCD's L2 works on one contiguous range of elements.
+#if SEM_GS_XCD
+    const unsigned per = gridDim.x / 8;  // the launcher rounds the grid up to 8 * per
+    const unsigned lb = (blockIdx.x % 8) * per + blockIdx.x / 8;
+#else
+    const unsigned lb = blockIdx.x;
+#endif
+    const int64_t tid = (int64_t)lb * VT + threadIdx.x;
     for (int f = 0; f < A.nfields; ++f) {
         if (A.skip && A.skip[f].stop) continue;
         T *u = A.u + f * A.n;
@@ -66,7 +90,7 @@ __global__ __launch_bounds__(VT) void k_gs(GsArgs<T> A)
         __shared__ double sh[VT];
         const AlphaJob &J = *A.alpha_job;
         for (int f = 0; f < A.nfields; ++f) {
-            const double pw = block_sum_fixed(J.partial + f * J.nblk, J.nblk, sh);
+            const double pw = block_sum_fixed<VT>(J.partial + f * J.nblk, J.nblk, sh);
             if (threadIdx.x == 0) {
                 CgScalars &s = J.scal[f];
                 if (!s.stop) {
@@ -80,6 +104,73 @@ __global__ __launch_bounds__(VT) void k_gs(GsArgs<T> A)
                 }
             }
         }
+    }
+}
+
+// Entry-parallel gather-scatter: lane t owns shared entry t (ascending global id,
+// groups never straddle a wave).  Every lane of a group reads the group's values
+// from its neighbour lanes and sums them in ascending local order from +0, so all
+// copies receive the identical, canonical sum; then each lane writes its own copy.
+// The shuffle loop runs max_group times for the whole wave (all lanes active).
+template <typename T>
+__global__ __launch_bounds__(VT) void k_gs_entries(GsArgs<T> A)
+{
+#if SEM_GS_XCD
+    const unsigned per = gridDim.x / 8;
+    const unsigned lb = (blockIdx.x % 8) * per + blockIdx.x / 8;
+#else
+    const unsigned lb = blockIdx.x;
+#endif
+    const int64_t t = (int64_t)lb * VT + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool in = t < A.nent;
+    const int32_t e = in ? A.ent_idx[t] : -1;
+    const unsigned meta = in ? A.ent_meta[t] : 0u;
+    const int pos = (int)(meta & 0xffu), cnt = (int)(meta >> 8);
+    const int lead = lane - pos;
+    for (int f = 0; f < A.nfields; ++f) {
+        if (A.skip && A.skip[f].stop) continue;
+        T *u = A.u + f * A.n;
+        const T v = (e >= 0) ? u[e] : T(0);
+        T s = T(0);
+        for (int q = 0; q < A.max_group; ++q) {
+            const int src = lead + q;
+            const T x = __shfl(v, src < 64 ? src : lane, 64);
+            if (q < cnt) s += x;
+        }
+        if (e >= 0) u[e] = s;
+    }
+    if (A.alpha_job && blockIdx.x == 0) {
+        __shared__ double sh[VT];
+        const AlphaJob &J = *A.alpha_job;
+        for (int f = 0; f < A.nfields; ++f) {
+            const double pw = block_sum_fixed<VT>(J.partial + f * J.nblk, J.nblk, sh);
+            if (threadIdx.x == 0) {
+                CgScalars &sc = J.scal[f];
+                if (!sc.stop) {
+                    if (!(pw > 0.0) || !isfinite(pw) || !isfinite(sc.rz)) {
+                        sc.stop = 1;
+                        sc.status = 2;
+                        sc.alpha = 0.0;
+                    } else {
+                        sc.alpha = sc.rz / pw;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Geometric factors between the exported planar layout and the internal one.
+__global__ __launch_bounds__(VT) void k_g_relayout(double *dst, const double *src, int64_t nelv, int64_t npe,
+                                                  int to_internal)
+{
+    const int64_t n = nelv * npe;
+    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < 6 * n; t += (int64_t)gridDim.x * VT) {
+        const int64_t f = t / n, p = t - f * n, e = p / npe, q = p - e * npe;
+        const int64_t o = goff((int)f, e, q, npe, n);
+        if (to_internal) dst[o] = src[t];
+        else dst[t] = src[o];
     }
 }
 
@@ -156,13 +247,13 @@ __global__ __launch_bounds__(VT) void k_cg_init(CgInitArgs<T> A)
 
 // Finish the initial reductions: rz, rr, bb; beta = 0; stop at once when b = 0
 // or the initial guess already meets the tolerance.
-__global__ __launch_bounds__(VT) void k_cg_start(CgFinishArgs A)
+__global__ __launch_bounds__(RT) void k_cg_start(CgFinishArgs A)
 {
-    __shared__ double sh[VT];
+    __shared__ double sh[RT];
     for (int f = 0; f < A.nfields; ++f) {
-        const double rz = block_sum_fixed(A.partial + (0 * A.nfields + f) * A.nblk, A.nblk, sh);
-        const double rr = block_sum_fixed(A.partial + (1 * A.nfields + f) * A.nblk, A.nblk, sh);
-        const double bb = block_sum_fixed(A.partial + (2 * A.nfields + f) * A.nblk, A.nblk, sh);
+        const double rz = block_sum_fixed<RT>(A.partial + (0 * A.nfields + f) * A.nblk, A.nblk, sh);
+        const double rr = block_sum_fixed<RT>(A.partial + (1 * A.nfields + f) * A.nblk, A.nblk, sh);
+        const double bb = block_sum_fixed<RT>(A.partial + (2 * A.nfields + f) * A.nblk, A.nblk, sh);
         if (threadIdx.x == 0) {
             CgScalars &s = A.scal[f];
             s.rz = rz;
@@ -227,12 +318,12 @@ __global__ __launch_bounds__(VT) void k_cg_update(CgUpdateArgs<T> A)
 }
 
 // End of one CG iteration: beta = rz_new / rz_old, convergence and iteration cap.
-__global__ __launch_bounds__(VT) void k_cg_finish(CgFinishArgs A)
+__global__ __launch_bounds__(RT) void k_cg_finish(CgFinishArgs A)
 {
-    __shared__ double sh[VT];
+    __shared__ double sh[RT];
     for (int f = 0; f < A.nfields; ++f) {
-        const double rz = block_sum_fixed(A.partial + (0 * A.nfields + f) * A.nblk, A.nblk, sh);
-        const double rr = block_sum_fixed(A.partial + (1 * A.nfields + f) * A.nblk, A.nblk, sh);
+        const double rz = block_sum_fixed<RT>(A.partial + (0 * A.nfields + f) * A.nblk, A.nblk, sh);
+        const double rr = block_sum_fixed<RT>(A.partial + (1 * A.nfields + f) * A.nblk, A.nblk, sh);
         if (threadIdx.x == 0) {
             CgScalars &s = A.scal[f];
             if (!s.stop) {
@@ -275,12 +366,12 @@ __global__ __launch_bounds__(VT) void k_dots(DotArgs A)
 }
 
 // out[q*nfields + f] = sum of partials, fixed order.
-__global__ __launch_bounds__(VT) void k_dots_finish(const double *partial, int64_t nblk, int nq,
+__global__ __launch_bounds__(RT) void k_dots_finish(const double *partial, int64_t nblk, int nq,
                                                      double *out)
 {
-    __shared__ double sh[VT];
+    __shared__ double sh[RT];
     for (int q = 0; q < nq; ++q) {
-        const double s = block_sum_fixed(partial + q * nblk, nblk, sh);
+        const double s = block_sum_fixed<RT>(partial + q * nblk, nblk, sh);
         if (threadIdx.x == 0) out[q] = s;
     }
 }
@@ -349,7 +440,7 @@ __global__ __launch_bounds__(VT) void k_fcg_scale_up(double *z, const float *y32
 // ------------------------------------------------------------------ host launchers
 using namespace sem;
 
-static unsigned stream_grid(int64_t n, unsigned cap = 16384)
+static unsigned stream_grid(int64_t n, unsigned cap = 2048)
 {
     int64_t g = (n + VT - 1) / VT;
     if (g < 1) g = 1;
@@ -357,24 +448,39 @@ static unsigned stream_grid(int64_t n, unsigned cap = 16384)
     return (unsigned)g;
 }
 
+static unsigned gs_grid(int64_t work)
+{
+    int64_t g = (work + VT - 1) / VT;
+    if (g < 1) g = 1;
+    return (unsigned)(8 * ((g + 7) / 8));  // multiple of 8: see the XCD mapping in k_gs
+}
+
 extern "C" {
 
 unsigned sem_vec_grid(int64_t n) { return stream_grid(n); }
 
-hipError_t sem_launch_gs_f64(const GsArgs<double> *A, hipStream_t st)
+}  // extern "C"
+
+// Entry-parallel kernel for groups of up to 64 copies, then (rarely) the per-group
+// kernel for larger groups.  The step-length fold runs in the first launch only.
+template <typename T>
+static hipError_t launch_gs_t(const GsArgs<T> *A, hipStream_t st)
 {
-    const int64_t work = A->npairs + A->nblocks;
-    const unsigned grid = (unsigned)((work + VT - 1) / VT > 0 ? (work + VT - 1) / VT : 1);
-    hipLaunchKernelGGL(k_gs<double>, dim3(grid), dim3(VT), 0, st, *A);
+    if (A->nent > 0) {
+        hipLaunchKernelGGL(k_gs_entries<T>, dim3(gs_grid(A->nent)), dim3(VT), 0, st, *A);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || A->npairs + A->nblocks == 0) return e;
+        GsArgs<T> B = *A;
+        B.alpha_job = nullptr;
+        hipLaunchKernelGGL(k_gs<T>, dim3(gs_grid(B.npairs + B.nblocks)), dim3(VT), 0, st, B);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_gs<T>, dim3(gs_grid(A->npairs + A->nblocks)), dim3(VT), 0, st, *A);
     return hipGetLastError();
 }
-hipError_t sem_launch_gs_f32(const GsArgs<float> *A, hipStream_t st)
-{
-    const int64_t work = A->npairs + A->nblocks;
-    const unsigned grid = (unsigned)((work + VT - 1) / VT > 0 ? (work + VT - 1) / VT : 1);
-    hipLaunchKernelGGL(k_gs<float>, dim3(grid), dim3(VT), 0, st, *A);
-    return hipGetLastError();
-}
+extern "C" {
+hipError_t sem_launch_gs_f64(const GsArgs<double> *A, hipStream_t st) { return launch_gs_t<double>(A, st); }
+hipError_t sem_launch_gs_f32(const GsArgs<float> *A, hipStream_t st) { return launch_gs_t<float>(A, st); }
 hipError_t sem_launch_mask(void *u, int is_f32, const int32_t *idx, int64_t m, int64_t n, int nfields,
                            hipStream_t st)
 {
@@ -404,6 +510,14 @@ hipError_t sem_launch_cast_f32_f64(float *dst, const double *src, double scale, 
     hipLaunchKernelGGL((k_cast<float, double>), dim3(stream_grid(m)), dim3(VT), 0, st, dst, src, scale, m);
     return hipGetLastError();
 }
+hipError_t sem_launch_g_relayout(double *dst, const double *src, int64_t nelv, int64_t npe, int to_internal,
+                                 hipStream_t st)
+{
+    if (nelv * npe == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_g_relayout, dim3(stream_grid(6 * nelv * npe)), dim3(VT), 0, st, dst, src, nelv, npe,
+                       to_internal);
+    return hipGetLastError();
+}
 hipError_t sem_launch_invert(double *d, const uint8_t *dir, int64_t n, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
@@ -422,7 +536,7 @@ hipError_t sem_launch_cg_init_f32(const CgInitArgs<float> *A, unsigned grid, hip
 }
 hipError_t sem_launch_cg_start(const CgFinishArgs *A, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(VT), 0, st, *A);
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(RT), 0, st, *A);
     return hipGetLastError();
 }
 hipError_t sem_launch_cg_update_f64(const CgUpdateArgs<double> *A, unsigned grid, hipStream_t st)
@@ -437,7 +551,7 @@ hipError_t sem_launch_cg_update_f32(const CgUpdateArgs<float> *A, unsigned grid,
 }
 hipError_t sem_launch_cg_finish(const CgFinishArgs *A, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(VT), 0, st, *A);
+    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(RT), 0, st, *A);
     return hipGetLastError();
 }
 hipError_t sem_launch_dots(const DotArgs *A, unsigned grid, hipStream_t st)
@@ -447,7 +561,7 @@ hipError_t sem_launch_dots(const DotArgs *A, unsigned grid, hipStream_t st)
 }
 hipError_t sem_launch_dots_finish(const double *partial, int64_t nblk, int nq, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_dots_finish, dim3(1), dim3(VT), 0, st, partial, nblk, nq, out);
+    hipLaunchKernelGGL(k_dots_finish, dim3(1), dim3(RT), 0, st, partial, nblk, nq, out);
     return hipGetLastError();
 }
 hipError_t sem_launch_residual(double *r, const double *b, const double *w, const double *dinv,
