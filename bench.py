@@ -6,7 +6,7 @@ operand u ~ U[-1,1] (seed 0), load vector U[-1,1] (seed 1) assembled and masked.
 
 One step = the whole hot path once:
   (a) R back-to-back ax_helm launches (the paper's matrix-vector benchmark loop,
-      Listing 2) on u, followed by one gs_op,
+      Listing 2) on u, followed by ten gs_op launches,
   (b) an FP64 Jacobi-PCG solve to relative residual 1e-10,
   (c) the mixed solve (FP64 flexible CG around FP32 Jacobi-PCG) to 1e-10.
 value = FP64 ax_helm GDOF/s = n_p / (average ax_helm launch time), from HIP events
@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--reps", type=int, default=20, help="ax_helm launches per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--inner-rtol", type=float, default=1e-4, dest="inner_rtol",
+                    help="nominal inner tolerance of the mixed solve")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one plain device copy of 2^27 doubles (reference "
                          "for counter scaling), --reps ax_helm launches, one gs_op and 20 PCG iterations")
@@ -100,19 +102,27 @@ def main():
 
     stream = torch.cuda.current_stream()
 
-    # copy bandwidth beta (the paper's STREAM-type beta): device-to-device copy of 1 GiB
+    # memory bandwidth beta as in the paper's model: STREAM triad a = b + s c over
+    # 3 x 1 GiB (libsem's triad kernel); also a plain 1 GiB device copy, which serves
+    # as the reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings.
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
+    tc = torch.empty_like(src).fill_(2.0)
     dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
+    sem.stream_triad(dst, src, tc, 3.0)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record(stream)
     for _ in range(5):
         dst.copy_(src)
-    e1.record(stream)
+    e[1].record(stream)
+    for _ in range(5):
+        sem.stream_triad(dst, src, tc, 3.0)
+    e[2].record(stream)
     torch.cuda.synchronize()
-    beta_copy = 2 * src.numel() * 8 * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
-    log(f"device copy bandwidth {beta_copy:.0f} GB/s")
-    del src, dst
+    beta_copy = 2 * src.numel() * 8 * 5 / (e[0].elapsed_time(e[1]) / 1e3) / 1e9
+    beta_triad = 3 * src.numel() * 8 * 5 / (e[1].elapsed_time(e[2]) / 1e3) / 1e9
+    log(f"device copy {beta_copy:.0f} GB/s, STREAM triad {beta_triad:.0f} GB/s")
+    del src, dst, tc
 
     if a.profile:
         sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
@@ -135,7 +145,8 @@ def main():
         for _ in range(a.reps):
             sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
         ev[1].record(stream)
-        P.gs.op(w)
+        for _ in range(10):
+            P.gs.op(w)
         ev[2].record(stream)
         t1 = time.perf_counter()
         x.zero_()
@@ -147,7 +158,7 @@ def main():
             t1 = time.perf_counter()
             x.zero_()
             infom = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, mixed=True,
-                                  inner_rtol=1e-4, inner_max_iter=5000, check_every=50)
+                                  inner_rtol=a.inner_rtol, inner_max_iter=5000, check_every=50)
             torch.cuda.synchronize()
             tm = time.perf_counter() - t1
         ev[3].record(stream)
@@ -165,6 +176,23 @@ def main():
                 record["trm"].append(infom[0]["true_rel_res"])
         return info64, infom
 
+    def ax_cold(reps=10):
+        """ax_helm with the last-level cache flushed before every launch (the paper's
+        cold-cache assumption between kernels): a 1 GiB read precedes each launch."""
+        flush = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        tot = 0.0
+        for _ in range(reps):
+            flush.sum()          # reads 1 GiB: the cache ends up holding clean, unrelated lines
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tot += e0.elapsed_time(e1)
+        del flush
+        return tot / reps / 1e3
+
     for i in range(a.warmup):
         step(None)
         log(f"warmup {i + 1}/{a.warmup} done")
@@ -179,6 +207,8 @@ def main():
                if rec["mixed_s"] else ""))
     torch.cuda.synchronize()
     total = time.perf_counter() - tb
+    cold_s = ax_cold()
+    log(f"ax cold-cache {cold_s * 1e6:.1f} us/launch")
 
     ax_s = sum(rec["ax_ms"]) / 1e3 / (a.reps * a.steps)
     gdofs = P.n / ax_s / 1e9
@@ -199,17 +229,21 @@ def main():
         "config": {"workload": wl.name, "elements": wl.nelv, "lx": wl.lx, "n_local": P.n,
                    "n_unique": wl.n_unique, "deformation": wl.eps, "h1": 1.0, "h2": 0.0,
                    "rtol": wl.rtol, "ax_launches_per_step": a.reps},
+        "ax_us_cold_cache": round(cold_s * 1e6, 2),
+        "ax_gdofs_cold_cache": round(P.n / cold_s / 1e9, 3),
+        "ax_frac_cold_cache": round(AX_WORDS_PER_POINT * 8 * P.n / cold_s / 1e9 / HBM_PEAK_GBS, 4),
+        "beta_triad_GBs": round(beta_triad, 1),
         "beta_copy_GBs": round(beta_copy, 1),
-        "ax_frac_of_copy_beta": round(achieved / beta_copy, 4),
+        "ax_frac_of_triad_beta": round(achieved / beta_triad, 4),
         "ax_us": round(ax_s * 1e6, 2),
-        "gs_us": round(float(np.mean(rec["gs_ms"])) * 1e3, 2),
+        "gs_us": round(float(np.mean(rec["gs_ms"])) * 1e3 / 10, 2),
         "pcg_fp64_solve_s": round(float(np.median(rec["pcg64_s"])), 4),
         "pcg_fp64_iters": int(np.median(rec["it64"])),
         "pcg_fp64_true_rel_res": float(np.max(rec["tr64"])),
         "pcg_fp64_ms_per_iter": round(float(np.median(rec["pcg64_s"])) / max(1, int(np.median(rec["it64"]))) * 1e3, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_ax_helm<8, double, 1>", "bytes_per_point": AX_WORDS_PER_POINT * 8},
+                     "kernel": "k_ax_helm<8, double, 1, false>", "bytes_per_point": AX_WORDS_PER_POINT * 8},
     }
     if rec["mixed_s"]:
         out.update({

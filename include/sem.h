@@ -175,7 +175,10 @@ typedef struct {
     int check_every;    /* host polls convergence every this many iterations (>= 1)   */
     int mixed;          /* 0: FP64 Jacobi-PCG; 1: FP64 flexible CG preconditioned by
                            an FP32 Jacobi-PCG inner solve (needs SEM_COEF_F32)         */
-    double inner_rtol;  /* mixed: relative tolerance of each inner solve               */
+    double inner_rtol;  /* mixed: nominal relative tolerance of each inner solve; an
+                           inner solve asks for no more than 0.1x the reduction still
+                           needed to reach rtol (never tighter than inner_rtol, at most
+                           0.5)                                                          */
     int inner_max_iter; /* mixed: iteration cap of each inner solve                    */
     int use_x0;         /* 1: x holds the initial guess on entry; 0: start from 0      */
 } sem_pcg_params;
@@ -196,6 +199,13 @@ typedef struct {
 sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef, sem_mesh msh,
                          sem_space Xh, sem_gs gs, const sem_pcg_params *params,
                          sem_pcg_info *info, void *stream);
+
+/* ---------------------------------------------------------------- measurement
+ * STREAM triad a = b + s*c over n FP64 values (device, caller-owned, a must not
+ * overlap b or c): the micro-benchmark the paper's performance model takes its
+ * memory bandwidth beta from (Section 8).  Enqueued on stream. */
+sem_status sem_stream_triad(double *a, const double *b, const double *c, double s, int64_t n,
+                            void *stream);
 
 /* ---------------------------------------------------------------- misc */
 const char *sem_last_error(void);

@@ -4,7 +4,8 @@ ax_kernels.hip is compiled once per supported lx (2..16) so the instantiations
 build in parallel; the objects are linked with the vector kernels, the host
 setup code and the C ABI into paper_2107_01243_amd/libsem.so.
 
-Usage: python -m paper_2107_01243_amd.build [--jobs N]
+Usage: python paper_2107_01243_amd/build.py [--jobs N]   (run by path: importing the
+package would load the library being built)
 """
 from __future__ import annotations
 

@@ -7,15 +7,17 @@
 //
 // Work decomposition ("pencil" layout).  One element is handled by lx*lx lanes.
 // A lane with in-element index t = a + lx*b owns, at different stages,
-//   r-pencil: the lx points (i = 0..lx-1, j = a, k = b)   (contiguous in HBM)
+//   t-pencil: the lx points (i = a, j = b, k = 0..lx-1)   (its home layout)
+//   r-pencil: the lx points (i = 0..lx-1, j = a, k = b)
 //   s-pencil: the lx points (i = a, j = 0..lx-1, k = b)
-//   t-pencil: the lx points (i = a, j = b, k = 0..lx-1)
-// Each 1-D derivative is then a register-only product with D in its even-odd form
-// (half the FMAs of the dense lx x lx product); its entries are wave-uniform (they
-// travel in the kernel-argument segment and are read through scalar loads).  LDS is used only to transpose pencils; every LDS row has
-// stride lx+1 so that r-pencil and s-pencil accesses avoid bank conflicts.
-// HBM traffic is the algorithmic minimum: each lane reads and writes whole
-// r-pencils (lx contiguous values), i.e. coalesced element-major streams.
+// In the home layout the lanes of an element read and write HBM at offsets
+// t + lx^2 k: for each k one wave instruction covers lx^2 consecutive values, so
+// every global access is fully coalesced.  Each 1-D derivative is a
+// register-only product with D in its even-odd form (half the FMAs of the dense
+// lx x lx product); its entries are wave-uniform (they travel in the
+// kernel-argument segment and are read through scalar loads).  LDS is used only
+// to transpose pencils; every LDS row has stride lx+1 so that the three pencil
+// access patterns are free of bank conflicts.
 //
 // This file is compiled once per lx (-DSEM_LX=<lx>) so that the per-lx
 // instantiations build in parallel; it exports plain host launchers.
@@ -27,23 +29,7 @@
 #ifndef SEM_LX
 #error "compile with -DSEM_LX=<lx>"
 #endif
-#ifndef SEM_WAVE_SYNC
-#define SEM_WAVE_SYNC 1
-#endif
-#ifndef SEM_G_LATE
-#define SEM_G_LATE 0
-#endif
-#ifndef SEM_MIN_WAVES
-#define SEM_MIN_WAVES 0
-#endif
-#ifndef SEM_NT_G
-#define SEM_NT_G 0
-#endif
-#if SEM_MIN_WAVES > 0
-#define SEM_BOUNDS(NT) __launch_bounds__((NT), SEM_MIN_WAVES)
-#else
 #define SEM_BOUNDS(NT) __launch_bounds__((NT))
-#endif
 
 namespace sem {
 
@@ -72,7 +58,11 @@ struct Shape {
         }
         return best;
     }
+#ifdef SEM_EPB8
+    static constexpr int EPB = (LX == 8) ? SEM_EPB8 : pick();
+#else
     static constexpr int EPB = pick();
+#endif
     static constexpr int NT = EPB * NP;
 };
 
@@ -88,7 +78,6 @@ struct Lds {
 template <int LX>
 __device__ __forceinline__ void esync()
 {
-#if SEM_WAVE_SYNC
     if constexpr (64 % (LX * LX) == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -96,9 +85,6 @@ __device__ __forceinline__ void esync()
     } else {
         __syncthreads();
     }
-#else
-    __syncthreads();
-#endif
 }
 
 // LDS index of point (i, j, k) inside one element buffer.
@@ -169,97 +155,96 @@ __device__ __forceinline__ void dtmul(const DEo<LX, T> &D, const T (&in)[LX], T 
     }
 }
 
-// Reference-space gradient of one field held as the lane's r-pencil `u`.
-// Returns ur, us, ut as r-pencils.  Uses both LDS buffers; ends synchronised.
+// Reference-space gradient of one field held as the lane's t-pencil `u`.
+// Returns ur, us, ut as t-pencils.  Uses both LDS buffers; ends synchronised.
 template <int LX, typename T>
 __device__ __forceinline__ void grad(const DEo<LX, T> &D, const T (&u)[LX], T *s0, T *s1,
                                      int a, int b, T (&ur)[LX], T (&us)[LX], T (&ut)[LX])
 {
-    dmul<LX, T>(D, u, ur);
+    dmul<LX, T>(D, u, ut);
 #pragma unroll
-    for (int i = 0; i < LX; ++i) s0[lidx<LX>(i, a, b)] = u[i];
+    for (int k = 0; k < LX; ++k) s0[lidx<LX>(a, b, k)] = u[k];
     esync<LX>();
     T v[LX], q[LX];
 #pragma unroll
-    for (int l = 0; l < LX; ++l) v[l] = s0[lidx<LX>(a, l, b)];   // s-pencil (i=a, k=b)
+    for (int l = 0; l < LX; ++l) v[l] = s0[lidx<LX>(l, a, b)];   // r-pencil (j=a, k=b)
     dmul<LX, T>(D, v, q);
     T v2[LX], q2[LX];
 #pragma unroll
-    for (int l = 0; l < LX; ++l) v2[l] = s0[lidx<LX>(a, b, l)];  // t-pencil (i=a, j=b)
+    for (int l = 0; l < LX; ++l) v2[l] = s0[lidx<LX>(a, l, b)];  // s-pencil (i=a, k=b)
     dmul<LX, T>(D, v2, q2);
 #pragma unroll
-    for (int m = 0; m < LX; ++m) s1[lidx<LX>(a, b, m)] = q2[m];
+    for (int m = 0; m < LX; ++m) s1[lidx<LX>(m, a, b)] = q[m];
     esync<LX>();
 #pragma unroll
-    for (int m = 0; m < LX; ++m) s0[lidx<LX>(a, m, b)] = q[m];
+    for (int m = 0; m < LX; ++m) s0[lidx<LX>(a, m, b)] = q2[m];
     esync<LX>();
 #pragma unroll
-    for (int i = 0; i < LX; ++i) {
-        us[i] = s0[lidx<LX>(i, a, b)];
-        ut[i] = s1[lidx<LX>(i, a, b)];
+    for (int k = 0; k < LX; ++k) {
+        ur[k] = s1[lidx<LX>(a, b, k)];
+        us[k] = s0[lidx<LX>(a, b, k)];
     }
     esync<LX>();
 }
 
-// acc = D_r^T wr + D_s^T ws + D_t^T wt for r-pencils wr, ws, wt.  Ends synchronised.
+// acc = D_r^T wr + D_s^T ws + D_t^T wt for t-pencils wr, ws, wt.  Ends synchronised.
 template <int LX, typename T>
 __device__ __forceinline__ void div(const DEo<LX, T> &D, const T (&wr)[LX], const T (&ws)[LX],
                                     const T (&wt)[LX], T *s0, T *s1, int a, int b, T (&acc)[LX])
 {
-    dtmul<LX, T>(D, wr, acc);
+    dtmul<LX, T>(D, wt, acc);
 #pragma unroll
-    for (int i = 0; i < LX; ++i) {
-        s0[lidx<LX>(i, a, b)] = ws[i];
-        s1[lidx<LX>(i, a, b)] = wt[i];
+    for (int k = 0; k < LX; ++k) {
+        s0[lidx<LX>(a, b, k)] = wr[k];
+        s1[lidx<LX>(a, b, k)] = ws[k];
     }
     esync<LX>();
     T v[LX], q[LX], v2[LX], q2[LX];
 #pragma unroll
-    for (int l = 0; l < LX; ++l) v[l] = s0[lidx<LX>(a, l, b)];
+    for (int l = 0; l < LX; ++l) v[l] = s0[lidx<LX>(l, a, b)];
 #pragma unroll
-    for (int l = 0; l < LX; ++l) v2[l] = s1[lidx<LX>(a, b, l)];
+    for (int l = 0; l < LX; ++l) v2[l] = s1[lidx<LX>(a, l, b)];
     dtmul<LX, T>(D, v, q);
     dtmul<LX, T>(D, v2, q2);
     esync<LX>();
 #pragma unroll
     for (int m = 0; m < LX; ++m) {
-        s0[lidx<LX>(a, m, b)] = q[m];
-        s1[lidx<LX>(a, b, m)] = q2[m];
+        s0[lidx<LX>(m, a, b)] = q[m];
+        s1[lidx<LX>(a, m, b)] = q2[m];
     }
     esync<LX>();
 #pragma unroll
-    for (int i = 0; i < LX; ++i) acc[i] += s0[lidx<LX>(i, a, b)] + s1[lidx<LX>(i, a, b)];
+    for (int k = 0; k < LX; ++k) acc[k] += s0[lidx<LX>(a, b, k)] + s1[lidx<LX>(a, b, k)];
     esync<LX>();
 }
 
+// A t-pencil in HBM: values p[k * lx^2], k = 0..lx-1 (p = element base + t).
 template <int LX, typename T>
 __device__ __forceinline__ void load_row(T (&r)[LX], const T *__restrict__ p, bool act)
 {
     if (act) {
 #pragma unroll
-        for (int i = 0; i < LX; ++i) r[i] = p[i];
+        for (int k = 0; k < LX; ++k) r[k] = p[k * LX * LX];
     } else {
 #pragma unroll
-        for (int i = 0; i < LX; ++i) r[i] = T(0);
+        for (int k = 0; k < LX; ++k) r[k] = T(0);
     }
 }
 
-// Geometric-factor rows are read exactly once per application: optionally as
-// non-temporal loads.
+// Geometric-factor pencils are streamed once per application and the six planes
+// (6 words per point) never fit the 256 MB last-level cache at production sizes, so
+// they are read with non-temporal loads: this keeps the cache for the vectors
+// (u, w, the Krylov vectors) that are reused between launches.
 template <int LX, typename T>
 __device__ __forceinline__ void load_g(T (&r)[LX], const T *__restrict__ p, bool act)
 {
-#if SEM_NT_G
-    if (act) {
+    if (!act) {
 #pragma unroll
-        for (int i = 0; i < LX; ++i) r[i] = __builtin_nontemporal_load(p + i);
-    } else {
-#pragma unroll
-        for (int i = 0; i < LX; ++i) r[i] = T(0);
+        for (int k = 0; k < LX; ++k) r[k] = T(0);
+        return;
     }
-#else
-    load_row<LX, T>(r, p, act);
-#endif
+#pragma unroll
+    for (int k = 0; k < LX; ++k) r[k] = __builtin_nontemporal_load(p + k * LX * LX);
 }
 
 template <int LX, typename T>
@@ -267,27 +252,75 @@ __device__ __forceinline__ void store_row(T *__restrict__ p, const T (&r)[LX], b
 {
     if (act) {
 #pragma unroll
-        for (int i = 0; i < LX; ++i) p[i] = r[i];
+        for (int k = 0; k < LX; ++k) p[k * LX * LX] = r[k];
     }
 }
 
-// Apply h1 * G at every point of the r-pencil (in place: ur,us,ut -> wr,ws,wt).
-template <int LX, typename T>
-__device__ __forceinline__ void apply_G(const T (&g)[6][LX], const T (&h1)[LX], T (&ur)[LX],
-                                        T (&us)[LX], T (&ut)[LX])
+// Helmholtz coefficients of one pencil.  GEN = false is the Poisson-type case
+// (h1 a scalar, no mass term): nothing per point is held, which keeps the
+// register footprint low; GEN = true handles h1 / h2 fields and the mass term.
+template <int LX, typename T, bool GEN>
+struct RowCoef {
+    T h1[GEN ? LX : 1];
+    T h2b[GEN ? LX : 1];  // h2 * B
+    bool mass = false;
+};
+
+template <int LX, typename T, bool GEN, typename Args>
+__device__ __forceinline__ void load_coef(RowCoef<LX, T, GEN> &c, const Args &A, int64_t row, bool act)
+{
+    if constexpr (GEN) {
+        if (A.h1) load_row<LX, T>(c.h1, A.h1 + row, act);
+        else {
+#pragma unroll
+            for (int i = 0; i < LX; ++i) c.h1[i] = A.h1s;
+        }
+        c.mass = A.h2 != nullptr || A.h2s != T(0);
+        if (c.mass) {
+            load_row<LX, T>(c.h2b, A.B + row, act);
+            if (A.h2) {
+                T h2[LX];
+                load_row<LX, T>(h2, A.h2 + row, act);
+#pragma unroll
+                for (int i = 0; i < LX; ++i) c.h2b[i] *= h2[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < LX; ++i) c.h2b[i] *= A.h2s;
+            }
+        }
+    }
+}
+
+// Apply h1 * G at every point of the pencil (in place: ur,us,ut -> wr,ws,wt).
+template <int LX, typename T, bool GEN>
+__device__ __forceinline__ void apply_G(const T (&g)[6][LX], const RowCoef<LX, T, GEN> &c, T h1s,
+                                        T (&ur)[LX], T (&us)[LX], T (&ut)[LX])
 {
 #pragma unroll
     for (int i = 0; i < LX; ++i) {
+        const T h = GEN ? c.h1[i] : h1s;
         const T r = ur[i], s = us[i], t = ut[i];
-        ur[i] = h1[i] * (g[0][i] * r + g[3][i] * s + g[4][i] * t);
-        us[i] = h1[i] * (g[3][i] * r + g[1][i] * s + g[5][i] * t);
-        ut[i] = h1[i] * (g[4][i] * r + g[5][i] * s + g[2][i] * t);
+        ur[i] = h * (g[0][i] * r + g[3][i] * s + g[4][i] * t);
+        us[i] = h * (g[3][i] * r + g[1][i] * s + g[5][i] * t);
+        ut[i] = h * (g[4][i] * r + g[5][i] * s + g[2][i] * t);
+    }
+}
+
+// w += h2 B u (general case only).
+template <int LX, typename T, bool GEN>
+__device__ __forceinline__ void add_mass(const RowCoef<LX, T, GEN> &c, const T (&u)[LX], T (&w)[LX])
+{
+    if constexpr (GEN) {
+        if (c.mass) {
+#pragma unroll
+            for (int i = 0; i < LX; ++i) w[i] = fma(c.h2b[i], u[i], w[i]);
+        }
     }
 }
 
 // ------------------------------------------------------------------ w = A_L u
 // NF fields share one read of G (and B, h1, h2).
-template <int LX, typename T, int NF>
+template <int LX, typename T, int NF, bool GEN>
 __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
@@ -298,52 +331,24 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo<LX, T>
     const int a = t % LX, b = t / LX;
     const int64_t e = (int64_t)blockIdx.x * S::EPB + slot;
     const bool act = e < A.nelv;
-    const int64_t row = e * (int64_t)(LX * LX * LX) + (int64_t)LX * t;
+    const int64_t row = e * (int64_t)(LX * LX * LX) + t;  // base of this lane's t-pencil
     T *s0 = lds.buf[0][slot], *s1 = lds.buf[1][slot];
 
     T g[6][LX];
-#if !SEM_G_LATE
 #pragma unroll
-    for (int f = 0; f < 6; ++f) load_g<LX, T>(g[f], A.G + goff(f, e, (int64_t)LX * t, (int64_t)(LX * LX * LX), A.n), act);
-#endif
-    T h1[LX], h2b[LX];
-    if (A.h1) load_row<LX, T>(h1, A.h1 + row, act);
-    else {
-#pragma unroll
-        for (int i = 0; i < LX; ++i) h1[i] = A.h1s;
-    }
-    const bool mass = A.h2 != nullptr || A.h2s != T(0);
-    if (mass) {
-        load_row<LX, T>(h2b, A.B + row, act);
-        if (A.h2) {
-            T h2[LX];
-            load_row<LX, T>(h2, A.h2 + row, act);
-#pragma unroll
-            for (int i = 0; i < LX; ++i) h2b[i] *= h2[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < LX; ++i) h2b[i] *= A.h2s;
-        }
-    }
+    for (int f = 0; f < 6; ++f) load_g<LX, T>(g[f], A.G + f * A.n + row, act);
+    RowCoef<LX, T, GEN> c;
+    load_coef<LX, T, GEN>(c, A, row, act);
 #pragma unroll 1
     for (int f = 0; f < NF; ++f) {
         T u[LX];
         load_row<LX, T>(u, A.u + f * A.n + row, act);
         T ur[LX], us[LX], ut[LX];
         grad<LX, T>(D, u, s0, s1, a, b, ur, us, ut);
-#if SEM_G_LATE
-        if (f == 0) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) load_g<LX, T>(g[q], A.G + goff(q, e, (int64_t)LX * t, (int64_t)(LX * LX * LX), A.n), act);
-        }
-#endif
-        apply_G<LX, T>(g, h1, ur, us, ut);
+        apply_G<LX, T, GEN>(g, c, A.h1s, ur, us, ut);
         T w[LX];
         div<LX, T>(D, ur, us, ut, s0, s1, a, b, w);
-        if (mass) {
-#pragma unroll
-            for (int i = 0; i < LX; ++i) w[i] = fma(h2b[i], u[i], w[i]);
-        }
+        add_mass<LX, T, GEN>(c, u, w);
         store_row<LX, T>(A.w + f * A.n + row, w, act);
     }
 }
@@ -353,8 +358,13 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo<LX, T>
 //   p = dinv * r + beta_f * p     (beta_f = 0 on the first iteration)
 //   w = A_L p,   partial_f += sum p * w   (the unassembled identity p^T A p = p_L^T A_L p_L)
 // Partials are per workgroup; a separate kernel reduces them in a fixed order.
-template <int LX, typename T, int NF>
-__global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DEo<LX, T> D)
+#ifdef SEM_CG_MINW
+#define SEM_CG_BOUNDS(NT) __launch_bounds__((NT), SEM_CG_MINW)
+#else
+#define SEM_CG_BOUNDS(NT) __launch_bounds__((NT))
+#endif
+template <int LX, typename T, int NF, bool GEN>
+__global__ SEM_CG_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
     __shared__ Lds<LX, T> lds;
@@ -365,31 +375,14 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DE
     const int a = t % LX, b = t / LX;
     const int64_t e = (int64_t)blockIdx.x * S::EPB + slot;
     const bool act = e < A.nelv;
-    const int64_t row = e * (int64_t)(LX * LX * LX) + (int64_t)LX * t;
+    const int64_t row = e * (int64_t)(LX * LX * LX) + t;  // base of this lane's t-pencil
     T *s0 = lds.buf[0][slot], *s1 = lds.buf[1][slot];
 
     T g[6][LX];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) load_g<LX, T>(g[f], A.G + goff(f, e, (int64_t)LX * t, (int64_t)(LX * LX * LX), A.n), act);
-    T h1[LX], h2b[LX];
-    if (A.h1) load_row<LX, T>(h1, A.h1 + row, act);
-    else {
-#pragma unroll
-        for (int i = 0; i < LX; ++i) h1[i] = A.h1s;
-    }
-    const bool mass = A.h2 != nullptr || A.h2s != T(0);
-    if (mass) {
-        load_row<LX, T>(h2b, A.B + row, act);
-        if (A.h2) {
-            T h2[LX];
-            load_row<LX, T>(h2, A.h2 + row, act);
-#pragma unroll
-            for (int i = 0; i < LX; ++i) h2b[i] *= h2[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < LX; ++i) h2b[i] *= A.h2s;
-        }
-    }
+    for (int f = 0; f < 6; ++f) load_g<LX, T>(g[f], A.G + f * A.n + row, act);
+    RowCoef<LX, T, GEN> c;
+    load_coef<LX, T, GEN>(c, A, row, act);
     T dinv[LX];
     load_row<LX, T>(dinv, A.dinv + row, act);
 
@@ -408,13 +401,10 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DE
         store_row<LX, T>(A.p + f * A.n + row, p, act);
         T ur[LX], us[LX], ut[LX];
         grad<LX, T>(D, p, s0, s1, a, b, ur, us, ut);
-        apply_G<LX, T>(g, h1, ur, us, ut);
+        apply_G<LX, T, GEN>(g, c, A.h1s, ur, us, ut);
         T w[LX];
         div<LX, T>(D, ur, us, ut, s0, s1, a, b, w);
-        if (mass) {
-#pragma unroll
-            for (int i = 0; i < LX; ++i) w[i] = fma(h2b[i], p[i], w[i]);
-        }
+        add_mass<LX, T, GEN>(c, p, w);
         store_row<LX, T>(A.w + f * A.n + row, w, act);
         double s = 0.0;
 #pragma unroll
@@ -451,7 +441,7 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_adjoint(AdjArgs<T> A, DEo<LX
     const int a = t % LX, b = t / LX;
     const int64_t e = (int64_t)blockIdx.x * S::EPB + slot;
     const bool act = e < A.nelv;
-    const int64_t row = e * (int64_t)(LX * LX * LX) + (int64_t)LX * t;
+    const int64_t row = e * (int64_t)(LX * LX * LX) + t;  // base of this lane's t-pencil
     T *s0 = lds.buf[0][slot], *s1 = lds.buf[1][slot];
 
     T u[LX], v[LX];
@@ -459,7 +449,7 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_adjoint(AdjArgs<T> A, DEo<LX
     load_row<LX, T>(v, A.v + row, act);
     T g[6][LX];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) load_g<LX, T>(g[f], A.G + goff(f, e, (int64_t)LX * t, (int64_t)(LX * LX * LX), A.n), act);
+    for (int f = 0; f < 6; ++f) load_g<LX, T>(g[f], A.G + f * A.n + row, act);
     T ur[LX], us[LX], ut[LX], vr[LX], vs[LX], vt[LX];
     grad<LX, T>(D, u, s0, s1, a, b, ur, us, ut);
     grad<LX, T>(D, v, s0, s1, a, b, vr, vs, vt);
@@ -519,7 +509,7 @@ __global__ __launch_bounds__(256) void k_geometry(GeomArgs A, DMat<LX, double> D
     const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
     for (int f = 0; f < 6; ++f) {
         const double d = C[0][ia[f]] * C[0][ib[f]] + C[1][ia[f]] * C[1][ib[f]] + C[2][ia[f]] * C[2][ib[f]];
-        A.G[goff(f, e, q, NPE, A.n)] = s * d;
+        A.G[f * A.n + p] = s * d;
     }
     A.B[p] = rho * J;
     if (!(J > 0.0)) atomicAdd(A.nbad, 1u);
@@ -548,15 +538,15 @@ __global__ __launch_bounds__(256) void k_diag(DiagArgs A, DMat<LX, double> D)
         const double cs = A.h1 ? A.h1[ps] : A.h1s;
         const double ct = A.h1 ? A.h1[pt] : A.h1s;
         const double dri = D.d[l * LX + i], dsj = D.d[l * LX + j], dtk = D.d[l * LX + k];
-        s += dri * dri * cr * G[goff(0, e, pr - b0, NPE, n)];
-        s += dsj * dsj * cs * G[goff(1, e, ps - b0, NPE, n)];
-        s += dtk * dtk * ct * G[goff(2, e, pt - b0, NPE, n)];
+        s += dri * dri * cr * G[pr];
+        s += dsj * dsj * cs * G[n + ps];
+        s += dtk * dtk * ct * G[2 * n + pt];
     }
     const double c = A.h1 ? A.h1[p] : A.h1s;
     const double di = D.d[i * LX + i], dj = D.d[j * LX + j], dk = D.d[k * LX + k];
-    s += 2.0 * di * dj * c * G[goff(3, e, q, NPE, n)];
-    s += 2.0 * di * dk * c * G[goff(4, e, q, NPE, n)];
-    s += 2.0 * dj * dk * c * G[goff(5, e, q, NPE, n)];
+    s += 2.0 * di * dj * c * G[3 * n + p];
+    s += 2.0 * di * dk * c * G[4 * n + p];
+    s += 2.0 * dj * dk * c * G[5 * n + p];
     const double c2 = A.h2 ? A.h2[p] : A.h2s;
     if (c2 != 0.0) s += c2 * A.B[p];
     A.d[p] = s;
@@ -604,10 +594,23 @@ hipError_t launch_ax(const sem::AxArgs<T> &A, const double *D, int nfields, hipS
     const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
     if (grid == 0) return hipSuccess;
     const auto Dm = make_deo<SEM_LX, T>(D);
-    if (nfields == 3)
-        hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 3>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
-    else
-        hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+#ifdef SEM_FORCE_GEN
+    const bool gen = true;
+#else
+    const bool gen = A.h1 || A.h2 || A.h2s != T(0);
+#endif
+#ifdef SEM_AX_LDS_PAD
+    const unsigned pad = sizeof(T) == 8 ? SEM_AX_LDS_PAD : 0;
+#else
+    const unsigned pad = 0;
+#endif
+    if (nfields == 3) {
+        if (gen) hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 3, true>), dim3(grid), dim3(S::NT), pad, st, A, Dm);
+        else hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 3, false>), dim3(grid), dim3(S::NT), pad, st, A, Dm);
+    } else {
+        if (gen) hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 1, true>), dim3(grid), dim3(S::NT), pad, st, A, Dm);
+        else hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 1, false>), dim3(grid), dim3(S::NT), pad, st, A, Dm);
+    }
     return hipGetLastError();
 }
 
@@ -618,10 +621,14 @@ hipError_t launch_cg(const sem::CgMatvecArgs<T> &A, const double *D, int nfields
     const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
     if (grid == 0) return hipSuccess;
     const auto Dm = make_deo<SEM_LX, T>(D);
-    if (nfields == 3)
-        hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
-    else
-        hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+    const bool gen = A.h1 || A.h2 || A.h2s != T(0);
+    if (nfields == 3) {
+        if (gen) hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3, true>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+        else hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3, false>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+    } else {
+        if (gen) hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1, true>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+        else hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1, false>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+    }
     return hipGetLastError();
 }
 

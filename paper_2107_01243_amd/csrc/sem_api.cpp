@@ -59,7 +59,7 @@ hipError_t sem_launch_fill_f64(double *, double, int64_t, hipStream_t);
 hipError_t sem_launch_fill_f32(float *, float, int64_t, hipStream_t);
 hipError_t sem_launch_cast_f32_f64(float *, const double *, double, int64_t, hipStream_t);
 hipError_t sem_launch_invert(double *, const uint8_t *, int64_t, hipStream_t);
-hipError_t sem_launch_g_relayout(double *, const double *, int64_t, int64_t, int, hipStream_t);
+hipError_t sem_launch_triad(double *, const double *, const double *, double, int64_t, hipStream_t);
 hipError_t sem_launch_cg_init_f64(const CgInitArgs<double> *, unsigned, hipStream_t);
 hipError_t sem_launch_cg_init_f32(const CgInitArgs<float> *, unsigned, hipStream_t);
 hipError_t sem_launch_cg_start(const CgFinishArgs *, hipStream_t);
@@ -488,7 +488,7 @@ sem_status dots(sem_coef c, sem_gs g, int nf, int nd, const double *const *a, co
 // b the assembled, masked right-hand side.  Per-field results land in W.h_scal.
 template <typename T>
 sem_status cg_run(sem_coef c, sem_gs g, int nf, T *x, const T *b, bool use_x0, T *r, T *p, T *w,
-                  const T *dinv, double rtol, int max_iter, int check_every, double *hist, int hist_len,
+                  const T *dinv, const double *rtol, int max_iter, int check_every, double *hist, int hist_len,
                   hipStream_t st)
 {
     Work &W = c->ws;
@@ -503,7 +503,7 @@ sem_status cg_run(sem_coef c, sem_gs g, int nf, T *x, const T *b, bool use_x0, T
     }
     for (int f = 0; f < nf; ++f) {
         CgScalars s{};
-        s.rtol = rtol;
+        s.rtol = rtol[f];
         s.max_iter = max_iter;
         W.h_scal[f] = s;
     }
@@ -855,7 +855,7 @@ sem_status sem_coef_create_from_G(sem_space Xh, sem_mesh msh, const double *G6_d
     hipStream_t st = S(stream);
     hipError_t e = hipSuccess;
     if (c->n > 0) {
-        e = sem_launch_g_relayout(c->G, G6_dev, c->nelv, c->n / c->nelv, 1, st);
+        e = hipMemcpyAsync(c->G, G6_dev, sizeof(double) * 6 * c->n, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(c->B, B_dev, sizeof(double) * c->n, hipMemcpyDeviceToDevice, st);
     }
     if (e != hipSuccess) {
@@ -909,7 +909,8 @@ sem_status sem_coef_export(sem_coef c, double *G6_dev, double *B_dev, void *stre
 {
     if (!c) return fail(SEM_ERR_INVALID, "coef is NULL");
     SEM_TRY(check_device(c->device));
-    if (G6_dev && c->n > 0) HIP_TRY(sem_launch_g_relayout(G6_dev, c->G, c->nelv, c->n / c->nelv, 0, S(stream)));
+    if (G6_dev && c->n > 0)
+        HIP_TRY(hipMemcpyAsync(G6_dev, c->G, sizeof(double) * 6 * c->n, hipMemcpyDeviceToDevice, S(stream)));
     if (B_dev) HIP_TRY(hipMemcpyAsync(B_dev, c->B, sizeof(double) * c->n, hipMemcpyDeviceToDevice, S(stream)));
     return SEM_OK;
 }
@@ -974,12 +975,25 @@ sem_status sem_jacobi_inverse(double *dinv, sem_coef coef, sem_mesh msh, sem_spa
     return SEM_OK;
 }
 
+// ------------------------------------------------------------------ measurement
+sem_status sem_stream_triad(double *a, const double *b, const double *c, double s, int64_t n, void *stream)
+{
+    if (n < 0) return fail(SEM_ERR_INVALID, "n < 0");
+    if (n == 0) return SEM_OK;
+    if (!a || !b || !c) return fail(SEM_ERR_INVALID, "NULL pointer");
+    const size_t bytes = (size_t)n * 8;
+    if (overlap(a, bytes, b, bytes) || overlap(a, bytes, c, bytes)) return fail(SEM_ERR_INVALID, "a overlaps b or c");
+    HIP_TRY(sem_launch_triad(a, b, c, s, n, S(stream)));
+    return SEM_OK;
+}
+
 // ------------------------------------------------------------------ solver
 static sem_status pcg_fp64(double *x, const double *b, int nf, sem_coef c, sem_gs g, const sem_pcg_params *P,
                            sem_pcg_info *info, hipStream_t st)
 {
     Work &W = c->ws;
-    SEM_TRY(cg_run<double>(c, g, nf, x, b, P->use_x0 != 0, W.r, W.p, W.w, c->dinv, P->rtol, P->max_iter,
+    const double rtol[3] = {P->rtol, P->rtol, P->rtol};
+    SEM_TRY(cg_run<double>(c, g, nf, x, b, P->use_x0 != 0, W.r, W.p, W.w, c->dinv, rtol, P->max_iter,
                            P->check_every, nullptr, 0, st));
     CgScalars res[3];
     std::memcpy(res, W.h_scal, sizeof(CgScalars) * nf);
@@ -1047,7 +1061,14 @@ static sem_status pcg_mixed(double *x, const double *b, int nf, sem_coef c, sem_
         HIP_TRY(hipMemcpyAsync(W.fcg, W.h_fcg, sizeof(double) * 4 * nf, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(W.done, W.h_done, sizeof(int) * nf, hipMemcpyHostToDevice, st));
         HIP_TRY(sem_launch_fcg_scale_down(W.r32, W.r, W.fcg + 3 * nf, W.done, n, nf, st));
-        SEM_TRY(cg_run<float>(c, g, nf, W.y32, W.r32, false, W.ri32, W.p32, W.w32, c->dinv32, P->inner_rtol,
+        // Inner tolerance: the nominal inner_rtol, loosened on the last outer steps to
+        // the reduction still needed (with a factor 0.1 of margin), at most 0.5.
+        double tau[3];
+        for (int f = 0; f < nf; ++f) {
+            const double need = (rr[f] > 0.0) ? 0.1 * P->rtol * std::sqrt(bb[f] / rr[f]) : 0.5;
+            tau[f] = std::min(0.5, std::max(P->inner_rtol, need));
+        }
+        SEM_TRY(cg_run<float>(c, g, nf, W.y32, W.r32, false, W.ri32, W.p32, W.w32, c->dinv32, tau,
                               P->inner_max_iter, std::max(1, P->check_every), nullptr, 0, st));
         for (int f = 0; f < nf; ++f) inner[f] += W.h_scal[f].iter;
         HIP_TRY(sem_launch_fcg_scale_up(W.z, W.y32, W.fcg + 2 * nf, n, nf, st));

@@ -4,25 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-// Internal layout of the geometric factors.  0: six planes of n values (the
-// exported layout).  1: element-blocked, factor f of element e at (e*6 + f)*lx^3,
-// so one element's six factors form one contiguous block.
-#ifndef SEM_G_BLOCKED
-#define SEM_G_BLOCKED 0
-#endif
-
 namespace sem {
-
-// Offset of factor f at in-element point q of element e (npe = lx^3, n = n_local).
-__host__ __device__ inline int64_t goff(int f, int64_t e, int64_t q, int64_t npe, int64_t n)
-{
-#if SEM_G_BLOCKED
-    (void)n;
-    return (e * 6 + f) * npe + q;
-#else
-    return f * n + e * npe + q;
-#endif
-}
 
 // 1-D GLL derivative matrix d[i*LX + l] = l_l'(xi_i), passed by value so that it
 // sits in the kernel-argument segment and is read with scalar loads.

@@ -161,17 +161,12 @@ __global__ __launch_bounds__(VT) void k_gs_entries(GsArgs<T> A)
     }
 }
 
-// Geometric factors between the exported planar layout and the internal one.
-__global__ __launch_bounds__(VT) void k_g_relayout(double *dst, const double *src, int64_t nelv, int64_t npe,
-                                                  int to_internal)
+// STREAM triad a = b + s c (bandwidth micro-benchmark).
+__global__ __launch_bounds__(VT) void k_triad(double *__restrict__ a, const double *__restrict__ b,
+                                              const double *__restrict__ c, double s, int64_t n)
 {
-    const int64_t n = nelv * npe;
-    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < 6 * n; t += (int64_t)gridDim.x * VT) {
-        const int64_t f = t / n, p = t - f * n, e = p / npe, q = p - e * npe;
-        const int64_t o = goff((int)f, e, q, npe, n);
-        if (to_internal) dst[o] = src[t];
-        else dst[t] = src[o];
-    }
+    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT)
+        a[t] = fma(s, c[t], b[t]);
 }
 
 // u[idx] = 0 for every listed index, each field.
@@ -510,12 +505,10 @@ hipError_t sem_launch_cast_f32_f64(float *dst, const double *src, double scale, 
     hipLaunchKernelGGL((k_cast<float, double>), dim3(stream_grid(m)), dim3(VT), 0, st, dst, src, scale, m);
     return hipGetLastError();
 }
-hipError_t sem_launch_g_relayout(double *dst, const double *src, int64_t nelv, int64_t npe, int to_internal,
-                                 hipStream_t st)
+hipError_t sem_launch_triad(double *a, const double *b, const double *c, double s, int64_t n, hipStream_t st)
 {
-    if (nelv * npe == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_g_relayout, dim3(stream_grid(6 * nelv * npe)), dim3(VT), 0, st, dst, src, nelv, npe,
-                       to_internal);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_triad, dim3(stream_grid(n, 8192)), dim3(VT), 0, st, a, b, c, s, n);
     return hipGetLastError();
 }
 hipError_t sem_launch_invert(double *d, const uint8_t *dir, int64_t n, hipStream_t st)

@@ -69,6 +69,7 @@ _SIGS = {
     "sem_jacobi_inverse": ([_vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "sem_pcg_solve": ([_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.POINTER(PcgParams),
                        C.POINTER(PcgInfo), _vp], C.c_int),
+    "sem_stream_triad": ([_vp, _vp, _vp, C.c_double, C.c_int64, _vp], C.c_int),
     "sem_last_error": ([], C.c_char_p),
     "sem_version": ([], C.c_char_p),
 }
@@ -319,6 +320,16 @@ def pcg_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, nfields: int = 1, 
     if st != SEM_OK and raise_on_fail:
         raise SemError(st, _L.sem_last_error().decode(errors="replace"))
     return out
+
+
+def stream_triad(a, b, c, s: float, stream=None):
+    """a = b + s c (FP64 device vectors): the STREAM-triad bandwidth probe."""
+    for t, nm in ((a, "a"), (b, "b"), (c, "c")):
+        _dev(t, a.numel(), nm)
+        if t.dtype != torch.float64:
+            raise TypeError("triad vectors must be float64")
+    _check(_L.sem_stream_triad(_ptr(a), _ptr(b), _ptr(c), float(s), a.numel(), _stream(stream)))
+    return a
 
 
 # ---------------------------------------------------------------- convenience
