@@ -39,6 +39,28 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+PROFILE_MD = os.path.join(ROOT, "profiles", "pcg_32x32x32_lx8_kernels.md")
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the summary is
+    missing or the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        text = open(PROFILE_MD).read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        h = hashlib.sha256()
+        for f in blob["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != blob["source_sha256"]:
+            return None
+        k = blob["kernels"][kernel]
+        return k["fetch_bytes"] + k["write_bytes"]
+    except (OSError, KeyError, IndexError, ValueError):
+        return None
+
+
 def cpu_baseline(wl, seconds=15.0):
     """The oracle's ax_helm on the same 32^3, lx=8 curved mesh, timed on the host."""
     import oracle
@@ -210,6 +232,7 @@ def main():
     cold_s = ax_cold()
     log(f"ax cold-cache {cold_s * 1e6:.1f} us/launch")
 
+    traffic = profiled_traffic("sem::k_ax_helm<8, double, 1, false>")
     ax_s = sum(rec["ax_ms"]) / 1e3 / (a.reps * a.steps)
     gdofs = P.n / ax_s / 1e9
     achieved = AX_WORDS_PER_POINT * 8 * P.n / ax_s / 1e9
@@ -242,7 +265,9 @@ def main():
         "pcg_fp64_true_rel_res": float(np.max(rec["tr64"])),
         "pcg_fp64_ms_per_iter": round(float(np.median(rec["pcg64_s"])) / max(1, int(np.median(rec["it64"]))) * 1e3, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "algorithmic_bytes": AX_WORDS_PER_POINT * 8 * P.n,
                      "kernel": "k_ax_helm<8, double, 1, false>", "bytes_per_point": AX_WORDS_PER_POINT * 8},
     }
     if rec["mixed_s"]:
