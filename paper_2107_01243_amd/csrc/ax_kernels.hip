@@ -58,11 +58,7 @@ struct Shape {
         }
         return best;
     }
-#ifdef SEM_EPB8
-    static constexpr int EPB = (LX == 8) ? SEM_EPB8 : pick();
-#else
     static constexpr int EPB = pick();
-#endif
     static constexpr int NT = EPB * NP;
 };
 
@@ -358,13 +354,8 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo<LX, T>
 //   p = dinv * r + beta_f * p     (beta_f = 0 on the first iteration)
 //   w = A_L p,   partial_f += sum p * w   (the unassembled identity p^T A p = p_L^T A_L p_L)
 // Partials are per workgroup; a separate kernel reduces them in a fixed order.
-#ifdef SEM_CG_MINW
-#define SEM_CG_BOUNDS(NT) __launch_bounds__((NT), SEM_CG_MINW)
-#else
-#define SEM_CG_BOUNDS(NT) __launch_bounds__((NT))
-#endif
 template <int LX, typename T, int NF, bool GEN>
-__global__ SEM_CG_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DEo<LX, T> D)
+__global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
     __shared__ Lds<LX, T> lds;
@@ -594,16 +585,8 @@ hipError_t launch_ax(const sem::AxArgs<T> &A, const double *D, int nfields, hipS
     const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
     if (grid == 0) return hipSuccess;
     const auto Dm = make_deo<SEM_LX, T>(D);
-#ifdef SEM_FORCE_GEN
-    const bool gen = true;
-#else
     const bool gen = A.h1 || A.h2 || A.h2s != T(0);
-#endif
-#ifdef SEM_AX_LDS_PAD
-    const unsigned pad = sizeof(T) == 8 ? SEM_AX_LDS_PAD : 0;
-#else
     const unsigned pad = 0;
-#endif
     if (nfields == 3) {
         if (gen) hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 3, true>), dim3(grid), dim3(S::NT), pad, st, A, Dm);
         else hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 3, false>), dim3(grid), dim3(S::NT), pad, st, A, Dm);

@@ -23,7 +23,16 @@
 
 namespace sem {
 
+#ifndef SEM_VCH
+#define SEM_VCH 2
+#endif
+
 constexpr int VT = 256;   // lanes per workgroup of the streaming kernels
+// Streaming kernels: workgroup b handles the contiguous chunk [b*CHUNK, (b+1)*CHUNK)
+// (VCH points per lane); the grid is as wide as the vector, and the number of
+// per-workgroup partial sums stays n / CHUNK.
+constexpr int VCH = SEM_VCH;
+constexpr int64_t CHUNK = (int64_t)VT * VCH;
 constexpr int RT = 1024;  // lanes of the single-workgroup reduction kernels
 
 // Sum `nblk` partials in a fixed order inside one workgroup of NTH lanes: lane t
@@ -165,8 +174,9 @@ __global__ __launch_bounds__(VT) void k_gs_entries(GsArgs<T> A)
 __global__ __launch_bounds__(VT) void k_triad(double *__restrict__ a, const double *__restrict__ b,
                                               const double *__restrict__ c, double s, int64_t n)
 {
-    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT)
-        a[t] = fma(s, c[t], b[t]);
+    const int64_t t_end = min(n, (int64_t)(blockIdx.x + 1) * CHUNK);
+#pragma unroll
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x; t < t_end; t += VT) a[t] = fma(s, c[t], b[t]);
 }
 
 // u[idx] = 0 for every listed index, each field.
@@ -181,7 +191,7 @@ __global__ __launch_bounds__(VT) void k_mask(T *u, const int32_t *idx, int64_t m
 template <typename T>
 __global__ __launch_bounds__(VT) void k_fill(T *u, T v, int64_t m)
 {
-    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < m; t += (int64_t)gridDim.x * VT)
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min((int64_t)(m), (int64_t)(blockIdx.x + 1) * CHUNK); t < t_end; t += VT)
         u[t] = v;
 }
 
@@ -189,7 +199,7 @@ __global__ __launch_bounds__(VT) void k_fill(T *u, T v, int64_t m)
 template <typename TD, typename TS>
 __global__ __launch_bounds__(VT) void k_cast(TD *dst, const TS *src, double scale, int64_t m)
 {
-    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < m; t += (int64_t)gridDim.x * VT)
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min((int64_t)(m), (int64_t)(blockIdx.x + 1) * CHUNK); t < t_end; t += VT)
         dst[t] = (TD)(scale * (double)src[t]);
 }
 
@@ -215,7 +225,7 @@ __global__ __launch_bounds__(VT) void k_cg_init(CgInitArgs<T> A)
     T *r = A.r + f * A.n;
     T *p = A.p + f * A.n;
     double rz = 0.0, rr = 0.0, bb = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < A.n; t += (int64_t)gridDim.x * VT) {
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min((int64_t)(A.n), (int64_t)(blockIdx.x + 1) * CHUNK); t < t_end; t += VT) {
         const T di = A.dinv[t];
         const T bi = b[t];
         const T ri = (di != T(0)) ? (w ? bi - w[t] : bi) : T(0);
@@ -282,9 +292,13 @@ __global__ __launch_bounds__(VT) void k_cg_update(CgUpdateArgs<T> A)
         T *r = A.r + f * A.n;
         const T *p = A.p + f * A.n;
         const T *w = A.w + f * A.n;
-        for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < A.n; t += (int64_t)gridDim.x * VT) {
+        const int64_t t_end = min(A.n, (int64_t)(blockIdx.x + 1) * CHUNK);
+#pragma unroll
+        for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x; t < t_end; t += VT) {
             const T di = A.dinv[t];
-            x[t] = fma(alpha, p[t], x[t]);
+            // x is touched only here: streamed with non-temporal hints so that the
+            // last-level cache keeps the vectors the next matvec and gs reuse.
+            __builtin_nontemporal_store(fma(alpha, p[t], __builtin_nontemporal_load(x + t)), x + t);
             T ri = r[t];
             if (di != T(0)) {
                 ri = fma(-alpha, w[t], ri);
@@ -344,7 +358,7 @@ __global__ __launch_bounds__(VT) void k_dots(DotArgs A)
     __shared__ double sh[4][VT];
     const int f = blockIdx.y;
     double acc[4] = {0, 0, 0, 0};
-    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < A.n; t += (int64_t)gridDim.x * VT) {
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min((int64_t)(A.n), (int64_t)(blockIdx.x + 1) * CHUNK); t < t_end; t += VT) {
         if (!A.owner[t]) continue;
         for (int q = 0; q < A.nd; ++q) acc[q] += A.a[q][f * A.n + t] * A.b[q][f * A.n + t];
     }
@@ -375,7 +389,7 @@ __global__ __launch_bounds__(RT) void k_dots_finish(const double *partial, int64
 __global__ __launch_bounds__(VT) void k_residual(double *r, const double *b, const double *w,
                                                  const double *dinv, int64_t n, int nfields)
 {
-    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT) {
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min((int64_t)(n), (int64_t)(blockIdx.x + 1) * CHUNK); t < t_end; t += VT) {
         const double di = dinv[t];
         for (int f = 0; f < nfields; ++f)
             r[f * n + t] = (di != 0.0) ? b[f * n + t] - w[f * n + t] : 0.0;
@@ -390,7 +404,7 @@ __global__ __launch_bounds__(VT) void k_fcg_dir(double *p, const double *z, cons
     const int f = blockIdx.y;
     if (done[f]) return;
     const double bf = beta[f];
-    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT)
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min((int64_t)(n), (int64_t)(blockIdx.x + 1) * CHUNK); t < t_end; t += VT)
         p[f * n + t] = z[f * n + t] - bf * p[f * n + t];
 }
 
@@ -403,7 +417,7 @@ __global__ __launch_bounds__(VT) void k_fcg_update(double *x, double *r, const d
     const int f = blockIdx.y;
     if (done[f]) return;
     const double a = alpha[f];
-    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT) {
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min((int64_t)(n), (int64_t)(blockIdx.x + 1) * CHUNK); t < t_end; t += VT) {
         x[f * n + t] = fma(a, p[f * n + t], x[f * n + t]);
         if (dinv[t] != 0.0) r[f * n + t] = fma(-a, q[f * n + t], r[f * n + t]);
     }
@@ -416,7 +430,7 @@ __global__ __launch_bounds__(VT) void k_fcg_scale_down(float *r32, const double 
 {
     const int f = blockIdx.y;
     const double s = done[f] ? 0.0 : inv_norm[f];
-    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT)
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min((int64_t)(n), (int64_t)(blockIdx.x + 1) * CHUNK); t < t_end; t += VT)
         r32[f * n + t] = (float)(s * r[f * n + t]);
 }
 
@@ -426,7 +440,7 @@ __global__ __launch_bounds__(VT) void k_fcg_scale_up(double *z, const float *y32
 {
     const int f = blockIdx.y;
     const double s = norm[f];
-    for (int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x; t < n; t += (int64_t)gridDim.x * VT)
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min((int64_t)(n), (int64_t)(blockIdx.x + 1) * CHUNK); t < t_end; t += VT)
         z[f * n + t] = s * (double)y32[f * n + t];
 }
 
@@ -435,12 +449,10 @@ __global__ __launch_bounds__(VT) void k_fcg_scale_up(double *z, const float *y32
 // ------------------------------------------------------------------ host launchers
 using namespace sem;
 
-static unsigned stream_grid(int64_t n, unsigned cap = 2048)
+static unsigned stream_grid(int64_t n)
 {
-    int64_t g = (n + VT - 1) / VT;
-    if (g < 1) g = 1;
-    if (g > cap) g = cap;
-    return (unsigned)g;
+    const int64_t g = (n + CHUNK - 1) / CHUNK;
+    return (unsigned)(g < 1 ? 1 : g);
 }
 
 static unsigned gs_grid(int64_t work)
@@ -508,7 +520,7 @@ hipError_t sem_launch_cast_f32_f64(float *dst, const double *src, double scale, 
 hipError_t sem_launch_triad(double *a, const double *b, const double *c, double s, int64_t n, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_triad, dim3(stream_grid(n, 8192)), dim3(VT), 0, st, a, b, c, s, n);
+    hipLaunchKernelGGL(k_triad, dim3(stream_grid(n)), dim3(VT), 0, st, a, b, c, s, n);
     return hipGetLastError();
 }
 hipError_t sem_launch_invert(double *d, const uint8_t *dir, int64_t n, hipStream_t st)
