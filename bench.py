@@ -8,7 +8,8 @@ One step = the whole hot path once:
   (a) R back-to-back ax_helm launches (the paper's matrix-vector benchmark loop,
       Listing 2) on u, followed by ten gs_op launches,
   (b) an FP64 Jacobi-PCG solve to relative residual 1e-10,
-  (c) the mixed solve (FP64 flexible CG around FP32 Jacobi-PCG) to 1e-10.
+  (c) the mixed solves to 1e-10: FP32 Jacobi-PCG with FP64 reliable updates, and
+      FP64 flexible CG around an FP32 Jacobi-PCG.
 value = FP64 ax_helm GDOF/s = n_p / (average ax_helm launch time), from HIP events
 on the launch stream over the timed steps.  The JSON line also carries both solve
 times, iteration counts, the roofline of the ax_helm kernel and the CPU oracle
@@ -155,8 +156,8 @@ def main():
         sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-30, max_iter=20, check_every=20,
                       raise_on_fail=False)
         x.zero_()
-        sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-10, mixed=True, inner_rtol=1e-4,
-                      inner_max_iter=20, max_iter=1, check_every=20, raise_on_fail=False)
+        sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-10, mixed="reliable", max_iter=20,
+                      check_every=20, raise_on_fail=False)
         torch.cuda.synchronize()
         log("profile pass done")
         return
@@ -175,14 +176,20 @@ def main():
         info64 = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, check_every=50)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t1
-        infom, tm = None, None
+        infom, tm, infof, tf = None, None, None, None
         if not a.no_mixed:
             t1 = time.perf_counter()
             x.zero_()
-            infom = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, mixed=True,
-                                  inner_rtol=a.inner_rtol, inner_max_iter=5000, check_every=50)
+            infom = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, mixed="reliable",
+                                  check_every=25)
             torch.cuda.synchronize()
             tm = time.perf_counter() - t1
+            t1 = time.perf_counter()
+            x.zero_()
+            infof = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, mixed="fcg",
+                                  inner_rtol=a.inner_rtol, inner_max_iter=5000, check_every=50)
+            torch.cuda.synchronize()
+            tf = time.perf_counter() - t1
         ev[3].record(stream)
         torch.cuda.synchronize()
         if record is not None:
@@ -196,6 +203,10 @@ def main():
                 record["outer"].append(infom[0]["iters"])
                 record["inner"].append(infom[0]["inner_iters"])
                 record["trm"].append(infom[0]["true_rel_res"])
+                record["fcg_s"].append(tf)
+                record["fcg_outer"].append(infof[0]["iters"])
+                record["fcg_inner"].append(infof[0]["inner_iters"])
+                record["fcg_tr"].append(infof[0]["true_rel_res"])
         return info64, infom
 
     def ax_cold(reps=10):
@@ -218,14 +229,16 @@ def main():
     for i in range(a.warmup):
         step(None)
         log(f"warmup {i + 1}/{a.warmup} done")
-    rec = {k: [] for k in ("ax_ms", "gs_ms", "pcg64_s", "it64", "tr64", "mixed_s", "outer", "inner", "trm")}
+    rec = {k: [] for k in ("ax_ms", "gs_ms", "pcg64_s", "it64", "tr64", "mixed_s", "outer", "inner", "trm",
+                           "fcg_s", "fcg_outer", "fcg_inner", "fcg_tr")}
     torch.cuda.synchronize()
     tb = time.perf_counter()
     for i in range(a.steps):
         step(rec)
         log(f"step {i + 1}/{a.steps}: ax {rec['ax_ms'][-1] / a.reps * 1e3:.1f} us/launch, "
             f"pcg64 {rec['pcg64_s'][-1]:.3f}s ({rec['it64'][-1]} it)"
-            + (f", mixed {rec['mixed_s'][-1]:.3f}s ({rec['outer'][-1]} outer / {rec['inner'][-1]} inner)"
+            + (f", mixed {rec['mixed_s'][-1]:.3f}s ({rec['outer'][-1]} replacements / {rec['inner'][-1]} it)"
+               f", fcg {rec['fcg_s'][-1]:.3f}s ({rec['fcg_outer'][-1]} outer / {rec['fcg_inner'][-1]} inner)"
                if rec["mixed_s"] else ""))
     torch.cuda.synchronize()
     total = time.perf_counter() - tb
@@ -273,10 +286,15 @@ def main():
     if rec["mixed_s"]:
         out.update({
             "pcg_mixed_solve_s": round(float(np.median(rec["mixed_s"])), 4),
-            "pcg_mixed_outer_iters": int(np.median(rec["outer"])),
-            "pcg_mixed_inner_iters": int(np.median(rec["inner"])),
+            "pcg_mixed_method": "FP32 Jacobi-PCG with FP64 reliable updates (residual replacement)",
+            "pcg_mixed_replacements": int(np.median(rec["outer"])),
+            "pcg_mixed_fp32_iters": int(np.median(rec["inner"])),
             "pcg_mixed_true_rel_res": float(np.max(rec["trm"])),
             "mixed_speedup_vs_fp64": round(float(np.median(rec["pcg64_s"])) / float(np.median(rec["mixed_s"])), 3),
+            "pcg_fcg_solve_s": round(float(np.median(rec["fcg_s"])), 4),
+            "pcg_fcg_outer_iters": int(np.median(rec["fcg_outer"])),
+            "pcg_fcg_inner_iters": int(np.median(rec["fcg_inner"])),
+            "pcg_fcg_true_rel_res": float(np.max(rec["fcg_tr"])),
         })
     if not a.no_cpu_baseline:
         del P, u, w, x, b

@@ -173,19 +173,30 @@ typedef struct {
                            recursive residual); <= 0: run exactly max_iter iterations */
     int max_iter;       /* outer iteration cap (>= 1)                                 */
     int check_every;    /* host polls convergence every this many iterations (>= 1)   */
-    int mixed;          /* 0: FP64 Jacobi-PCG; 1: FP64 flexible CG preconditioned by
-                           an FP32 Jacobi-PCG inner solve (needs SEM_COEF_F32)         */
+    int mixed;          /* 0: FP64 Jacobi-PCG.
+                           1: Jacobi-PCG iterating in FP32 (FP32 operator, vectors and
+                              preconditioner, FP64 dot accumulation) with FP64 reliable
+                              updates: whenever the FP32 residual has dropped by `delta`,
+                              x is accumulated in FP64, the true residual b - A x is
+                              recomputed with the FP64 operator and replaces the FP32 one
+                              (the search direction is kept); convergence is decided on
+                              that FP64 residual.  max_iter caps the FP32 iterations.
+                           2: FP64 flexible CG preconditioned by an FP32 Jacobi-PCG
+                              inner solve (inner_rtol, inner_max_iter).
+                           1 and 2 need a coef created with SEM_COEF_F32.               */
     double inner_rtol;  /* mixed: nominal relative tolerance of each inner solve; an
                            inner solve asks for no more than 0.1x the reduction still
                            needed to reach rtol (never tighter than inner_rtol, at most
                            0.5)                                                          */
     int inner_max_iter; /* mixed: iteration cap of each inner solve                    */
     int use_x0;         /* 1: x holds the initial guess on entry; 0: start from 0      */
+    double delta;       /* mixed == 1: residual-replacement factor in (0, 1); 0 -> 0.5 */
 } sem_pcg_params;
 
 typedef struct {
-    int iters;          /* outer iterations performed                                  */
-    int inner_iters;    /* mixed: total inner FP32 iterations                          */
+    int iters;          /* FP64: CG iterations; mixed 1: residual replacements;
+                           mixed 2: outer flexible-CG iterations                        */
+    int inner_iters;    /* mixed: total FP32 CG iterations                             */
     int converged;      /* 1 when rel_res <= rtol                                      */
     double rel_res;     /* recursive |r|/|b| at exit                                   */
     double true_rel_res;/* |b - A x|/|b| recomputed in FP64 at exit                    */

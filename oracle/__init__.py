@@ -229,7 +229,8 @@ class Problem:
     A = mask QQ^T A_L(h1, h2) in local layout (Eq. 9-10 with Eq. 5 imposed by masking).
     """
 
-    def __init__(self, nx, lx, eps=0.0, h1=1.0, h2=0.0, ny=None, nz=None):
+    def __init__(self, nx, lx, eps=0.0, h1=1.0, h2=0.0, ny=None, nz=None, progress=None):
+        say = progress or (lambda msg: None)
         ny = nx if ny is None else ny
         nz = nx if nz is None else nz
         self.lx = lx
@@ -240,10 +241,14 @@ class Problem:
         m = box_mesh(nx, ny, nz, lx, eps)
         self.glb, self.dirichlet = m["glb"], m["dirichlet"]
         self.x, self.y, self.z = m["x"], m["y"], m["z"]
+        say("oracle: mesh done")
         self.G, self.B, self.J = geometry(lx, self.D, self.w, self.x, self.y, self.z)
+        say("oracle: geometry done")
         self.gs = GS(self.glb)
+        say("oracle: gather-scatter groups done")
         self.mult = self.gs.mult()
         self.set_coef(h1, h2)
+        say("oracle: Jacobi diagonal done")
 
     def set_coef(self, h1, h2):
         self.h1, self.h2 = h1, h2

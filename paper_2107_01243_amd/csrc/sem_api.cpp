@@ -67,6 +67,12 @@ hipError_t sem_launch_cg_update_f64(const CgUpdateArgs<double> *, unsigned, hipS
 hipError_t sem_launch_cg_update_f32(const CgUpdateArgs<float> *, unsigned, hipStream_t);
 hipError_t sem_launch_cg_finish(const CgFinishArgs *, hipStream_t);
 hipError_t sem_launch_dots(const DotArgs *, unsigned, hipStream_t);
+hipError_t sem_launch_rel_restart(const RelRestartArgs *, unsigned, hipStream_t);
+hipError_t sem_launch_cg_replace_f64(const double *, const double *, const uint8_t *, const int *, double *, int64_t,
+                                     int, hipStream_t);
+hipError_t sem_launch_cg_resume(const CgFinishArgs *, const int *, hipStream_t);
+hipError_t sem_launch_rel_resume(const CgFinishArgs *, RelState *, int, hipStream_t);
+hipError_t sem_launch_add_f32(double *, const float *, const int *, int64_t, int, hipStream_t);
 hipError_t sem_launch_dots_finish(const double *, int64_t, int, double *, hipStream_t);
 hipError_t sem_launch_residual(double *, const double *, const double *, const double *, int64_t, int,
                                hipStream_t);
@@ -228,11 +234,15 @@ struct Work {
     double *h_fcg = nullptr;        // pinned mirror
     int *done = nullptr;            // device [3]
     int *h_done = nullptr;          // pinned mirror
+    RelState *rel = nullptr;        // device [3], reliable-update mixed solve
+    RelState *h_rel = nullptr;      // pinned mirror
     void release()
     {
         dfree(r); dfree(p); dfree(w); dfree(z); dfree(q);
         dfree(r32); dfree(y32); dfree(p32); dfree(w32); dfree(ri32);
-        dfree(partial); dfree(scal); dfree(job64); dfree(job32); dfree(dots); dfree(fcg); dfree(done);
+        dfree(partial); dfree(scal); dfree(job64); dfree(job32); dfree(dots); dfree(fcg); dfree(done); dfree(rel);
+        if (h_rel) (void)hipHostFree(h_rel);
+        h_rel = nullptr;
         if (h_scal) (void)hipHostFree(h_scal);
         if (h_dots) (void)hipHostFree(h_dots);
         if (h_fcg) (void)hipHostFree(h_fcg);
@@ -450,6 +460,8 @@ sem_status ensure_work(sem_coef c, int nf, bool mixed)
     HIP_TRY(hipHostMalloc((void **)&W.h_dots, sizeof(double) * 4 * nf, hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&W.h_fcg, sizeof(double) * 4 * nf, hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&W.h_done, sizeof(int) * nf, hipHostMallocDefault));
+    SEM_TRY(dalloc(&W.rel, nf));
+    HIP_TRY(hipHostMalloc((void **)&W.h_rel, sizeof(RelState) * nf, hipHostMallocDefault));
     const AlphaJob j64{W.partial, fns(c->lx).nblk64(c->nelv), W.scal};
     const AlphaJob j32{W.partial, fns(c->lx).nblk32(c->nelv), W.scal};
     HIP_TRY(hipMemcpy(W.job64, &j64, sizeof(AlphaJob), hipMemcpyHostToDevice));
@@ -484,6 +496,10 @@ sem_status dots(sem_coef c, sem_gs g, int nf, int nd, const double *const *a, co
     return SEM_OK;
 }
 
+template <typename T>
+sem_status cg_iterate(sem_coef c, sem_gs g, int nf, T *x, T *r, T *p, T *w, const T *dinv, int max_iter,
+                      int check_every, double *hist, int hist_len, hipStream_t st);
+
 // Jacobi-PCG in precision T on nf fields.  x is the iterate (zeroed unless use_x0),
 // b the assembled, masked right-hand side.  Per-field results land in W.h_scal.
 template <typename T>
@@ -493,7 +509,6 @@ sem_status cg_run(sem_coef c, sem_gs g, int nf, T *x, const T *b, bool use_x0, T
 {
     Work &W = c->ws;
     const int64_t n = c->n;
-    const bool f64 = sizeof(T) == 8;
     if (use_x0) {
         SEM_TRY(launch_ax<T>(c, w, x, nf, st));
         SEM_TRY(launch_gs<T>(w, nf, g, nullptr, nullptr, st));
@@ -525,8 +540,19 @@ sem_status cg_run(sem_coef c, sem_gs g, int nf, T *x, const T *b, bool use_x0, T
         CgFinishArgs F{W.partial, (int64_t)vg, W.scal, hist, hist_len, nf};
         HIP_TRY(sem_launch_cg_start(&F, st));
     }
-    const AlphaJob *job = f64 ? W.job64 : W.job32;
+    return cg_iterate<T>(c, g, nf, x, r, p, w, dinv, max_iter, check_every, hist, hist_len, st);
+}
 
+// Iterate the CG state held in W.scal until every field has stopped.
+template <typename T>
+sem_status cg_iterate(sem_coef c, sem_gs g, int nf, T *x, T *r, T *p, T *w, const T *dinv, int max_iter,
+                      int check_every, double *hist, int hist_len, hipStream_t st)
+{
+    Work &W = c->ws;
+    const int64_t n = c->n;
+    const bool f64 = sizeof(T) == 8;
+    const unsigned vg = sem_vec_grid(n);
+    const AlphaJob *job = f64 ? W.job64 : W.job32;
     CgMatvecArgs<T> M;
     M.p = p;
     M.w = w;
@@ -544,7 +570,6 @@ sem_status cg_run(sem_coef c, sem_gs g, int nf, T *x, const T *b, bool use_x0, T
     M.partial = W.partial;
     CgUpdateArgs<T> U{x, r, p, w, dinv, g->d_owner, W.scal, W.partial, n, nf};
     CgFinishArgs F{W.partial, (int64_t)vg, W.scal, hist, hist_len, nf};
-
     if (check_every < 1) check_every = 1;
     const int64_t max_batches = (int64_t)(max_iter + check_every - 1) / check_every + 2;
     // first poll right after initialisation (b = 0 or an exact initial guess)
@@ -995,15 +1020,34 @@ static sem_status pcg_fp64(double *x, const double *b, int nf, sem_coef c, sem_g
     const double rtol[3] = {P->rtol, P->rtol, P->rtol};
     SEM_TRY(cg_run<double>(c, g, nf, x, b, P->use_x0 != 0, W.r, W.p, W.w, c->dinv, rtol, P->max_iter,
                            P->check_every, nullptr, 0, st));
+    // A field counts as converged only when its true residual |b - A x| / |b| meets
+    // rtol.  When the recursive residual has drifted below it, the true residual
+    // (left in W.r by true_residual) replaces it and the iteration continues with
+    // its search direction.
+    double tr[3];
+    for (int round = 0;; ++round) {
+        SEM_TRY(true_residual(c, g, nf, x, b, tr, st));
+        bool any = false;
+        for (int f = 0; f < nf; ++f) {
+            const CgScalars &s = W.h_scal[f];
+            W.h_done[f] = (s.status == 0 && P->rtol > 0 && s.bb > 0 && tr[f] > P->rtol && s.iter < P->max_iter) ? 1 : 0;
+            any = any || W.h_done[f];
+        }
+        if (!any || round >= 16) break;
+        const unsigned vg = sem_vec_grid(c->n);
+        HIP_TRY(hipMemcpyAsync(W.done, W.h_done, sizeof(int) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(sem_launch_cg_replace_f64(W.r, c->dinv, g->d_owner, W.done, W.partial, c->n, nf, st));
+        CgFinishArgs F{W.partial, (int64_t)vg, W.scal, nullptr, 0, nf};
+        HIP_TRY(sem_launch_cg_resume(&F, W.done, st));
+        SEM_TRY(cg_iterate<double>(c, g, nf, x, W.r, W.p, W.w, c->dinv, P->max_iter, P->check_every, nullptr, 0, st));
+    }
     CgScalars res[3];
     std::memcpy(res, W.h_scal, sizeof(CgScalars) * nf);
-    double tr[3];
-    SEM_TRY(true_residual(c, g, nf, x, b, tr, st));
     sem_status out = SEM_OK;
     for (int f = 0; f < nf; ++f) {
         const CgScalars &s = res[f];
         const double rel = s.bb == 0.0 ? 0.0 : std::sqrt(s.rr / s.bb);
-        const bool conv = s.status == 0 && std::isfinite(rel) && (P->rtol <= 0 || rel <= P->rtol);
+        const bool conv = s.status == 0 && std::isfinite(rel) && (P->rtol <= 0 || (rel <= P->rtol && tr[f] <= P->rtol));
         if (info) {
             info[f].iters = s.iter;
             info[f].inner_iters = 0;
@@ -1012,6 +1056,111 @@ static sem_status pcg_fp64(double *x, const double *b, int nf, sem_coef c, sem_g
             info[f].true_rel_res = tr[f];
         }
         if (s.status == 2) out = fail(SEM_ERR_BREAKDOWN, "CG breakdown in field %d at iteration %d", f, s.iter);
+        else if (!conv && out == SEM_OK)
+            out = fail(SEM_ERR_NOT_CONVERGED, "field %d: |r|/|b| = %.3e after %d iterations", f, rel, s.iter);
+    }
+    return out;
+}
+
+// Jacobi-PCG iterating in FP32 with FP64 reliable updates (residual replacement):
+// the FP32 iteration runs in segments; a segment ends once its residual has dropped
+// by delta (device side); then x += x32 in FP64, r = b - A64 x in FP64, the FP32
+// residual is replaced by it and the iteration resumes with its search direction.
+// Convergence is decided on the FP64 true residual.
+static sem_status pcg_mixed_reliable(double *x, const double *b, int nf, sem_coef c, sem_gs g,
+                                     const sem_pcg_params *P, sem_pcg_info *info, hipStream_t st)
+{
+    Work &W = c->ws;
+    const int64_t n = c->n;
+    const int64_t nn = n * nf;
+    const unsigned vg = sem_vec_grid(n);
+    // FP64 residual of the initial guess
+    if (P->use_x0) {
+        SEM_TRY(launch_ax<double>(c, W.w, x, nf, st));
+        SEM_TRY(launch_gs<double>(W.w, nf, g, nullptr, nullptr, st));
+        HIP_TRY(sem_launch_residual(W.r, b, W.w, c->dinv, n, nf, st));
+    } else {
+        HIP_TRY(sem_launch_fill_f64(x, 0.0, nn, st));
+        HIP_TRY(hipMemcpyAsync(W.r, b, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+    }
+    double bb[3];
+    {
+        const double *a[1] = {b};
+        SEM_TRY(dots(c, g, nf, 1, a, a, bb, st));
+    }
+    const double delta = (P->delta > 0.0 && P->delta < 1.0) ? P->delta : 0.5;
+    for (int f = 0; f < nf; ++f) {
+        W.h_rel[f] = RelState{bb[f], 0.0, P->rtol, delta, 0, 0};
+        CgScalars s{};
+        s.max_iter = P->max_iter;
+        W.h_scal[f] = s;
+    }
+    HIP_TRY(hipMemcpyAsync(W.rel, W.h_rel, sizeof(RelState) * nf, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(W.scal, W.h_scal, sizeof(CgScalars) * nf, hipMemcpyHostToDevice, st));
+    RelRestartArgs RA{W.r, W.r32, W.y32, W.p32, c->dinv32, g->d_owner, W.rel, W.partial, n, nf};
+    CgFinishArgs RF{W.partial, (int64_t)vg, W.scal, nullptr, 0, nf};
+    HIP_TRY(sem_launch_rel_restart(&RA, vg, st));
+    HIP_TRY(sem_launch_rel_resume(&RF, W.rel, 1, st));
+    RA.p32 = nullptr;  // later segments keep the search direction
+
+    CgMatvecArgs<float> M;
+    M.p = W.p32;
+    M.w = W.w32;
+    M.r = W.r32;
+    M.dinv = c->dinv32;
+    M.G = c->G32; M.B = c->B32; M.h1 = c->h1_32; M.h2 = c->h2_32;
+    M.h1s = (float)c->h1s; M.h2s = (float)c->h2s;
+    M.n = n;
+    M.nelv = c->nelv;
+    M.scal = W.scal;
+    M.partial = W.partial;
+    CgUpdateArgs<float> U{W.y32, W.r32, W.p32, W.w32, c->dinv32, g->d_owner, W.scal, W.partial, n, nf};
+    CgFinishArgs F{W.partial, (int64_t)vg, W.scal, nullptr, 0, nf};
+    const int check_every = std::max(1, P->check_every);
+    const int64_t max_polls = (int64_t)P->max_iter / check_every + 64 * 64;
+    for (int64_t poll = 0; poll < max_polls; ++poll) {
+        HIP_TRY(hipMemcpyAsync(W.h_scal, W.scal, sizeof(CgScalars) * nf, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(W.h_rel, W.rel, sizeof(RelState) * nf, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        bool all_stopped = true, all_done = true;
+        for (int f = 0; f < nf; ++f) {
+            all_stopped = all_stopped && W.h_scal[f].stop;
+            all_done = all_done && W.h_rel[f].done;
+        }
+        if (all_done) break;
+        if (all_stopped) {
+            // end of a segment: accumulate x and replace the residual (fields not done)
+            for (int f = 0; f < nf; ++f) W.h_done[f] = W.h_rel[f].done;
+            HIP_TRY(hipMemcpyAsync(W.done, W.h_done, sizeof(int) * nf, hipMemcpyHostToDevice, st));
+            HIP_TRY(sem_launch_add_f32(x, W.y32, W.done, n, nf, st));
+            SEM_TRY(launch_ax<double>(c, W.w, x, nf, st));
+            SEM_TRY(launch_gs<double>(W.w, nf, g, nullptr, nullptr, st));
+            HIP_TRY(sem_launch_residual(W.r, b, W.w, c->dinv, n, nf, st));
+            HIP_TRY(sem_launch_rel_restart(&RA, vg, st));
+            HIP_TRY(sem_launch_rel_resume(&RF, W.rel, 0, st));
+            continue;
+        }
+        for (int it = 0; it < check_every; ++it) {
+            HIP_TRY(fns(c->lx).cg32(&M, c->Xh->D, nf, st));
+            SEM_TRY(launch_gs<float>(W.w32, nf, g, W.scal, W.job32, st));
+            HIP_TRY(sem_launch_cg_update_f32(&U, vg, st));
+            HIP_TRY(sem_launch_cg_finish(&F, st));
+        }
+    }
+    sem_status out = SEM_OK;
+    for (int f = 0; f < nf; ++f) {
+        const RelState &R = W.h_rel[f];
+        const CgScalars &s = W.h_scal[f];
+        const double rel = R.bb64 == 0.0 ? 0.0 : std::sqrt(R.rr64 / R.bb64);
+        const bool conv = R.done && s.status == 0 && std::isfinite(rel) && rel <= P->rtol;
+        if (info) {
+            info[f].iters = R.outer;
+            info[f].inner_iters = s.iter;
+            info[f].converged = conv ? 1 : 0;
+            info[f].rel_res = rel;
+            info[f].true_rel_res = rel;  // the FP64 true residual of the returned x
+        }
+        if (s.status == 2) out = fail(SEM_ERR_BREAKDOWN, "CG breakdown in field %d", f);
         else if (!conv && out == SEM_OK)
             out = fail(SEM_ERR_NOT_CONVERGED, "field %d: |r|/|b| = %.3e after %d iterations", f, rel, s.iter);
     }
@@ -1047,7 +1196,10 @@ static sem_status pcg_mixed(double *x, const double *b, int nf, sem_coef c, sem_
         if (!std::isfinite(bb[f]) || !std::isfinite(rr[f])) { done[f] = 1; status[f] = 2; }
         else if (bb[f] == 0.0 || (P->rtol > 0 && std::sqrt(rr[f] / bb[f]) <= P->rtol)) done[f] = 1;
     }
-    for (int k = 0; k < P->max_iter; ++k) {
+    double tr[3] = {0, 0, 0};
+    int k = 0;
+    for (int round = 0;; ++round) {
+    for (; k < P->max_iter; ++k) {
         bool all = true;
         for (int f = 0; f < nf; ++f) all = all && done[f];
         if (all) break;
@@ -1122,12 +1274,23 @@ static sem_status pcg_mixed(double *x, const double *b, int nf, sem_coef c, sem_
             }
         }
     }
-    double tr[3];
+    // verify on the true residual; fields whose recursive residual drifted below it
+    // continue from the true residual (left in W.r by true_residual)
     SEM_TRY(true_residual(c, g, nf, x, b, tr, st));
+    bool again = false;
+    for (int f = 0; f < nf; ++f) {
+        if (status[f] == 0 && bb[f] > 0.0 && tr[f] > P->rtol && k < P->max_iter) {
+            done[f] = 0;
+            rr[f] = tr[f] * tr[f] * bb[f];
+            again = true;
+        }
+    }
+    if (!again || round >= 16) break;
+    }
     sem_status out = SEM_OK;
     for (int f = 0; f < nf; ++f) {
         const double rel = bb[f] == 0.0 ? 0.0 : std::sqrt(rr[f] / bb[f]);
-        const bool conv = status[f] == 0 && std::isfinite(rel) && (P->rtol <= 0 || rel <= P->rtol);
+        const bool conv = status[f] == 0 && std::isfinite(rel) && (P->rtol <= 0 || (rel <= P->rtol && tr[f] <= P->rtol));
         if (info) {
             info[f].iters = iters[f];
             info[f].inner_iters = inner[f];
@@ -1152,11 +1315,16 @@ sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef,
     const sem_pcg_params &P = *params;
     if (P.max_iter < 1) return fail(SEM_ERR_INVALID, "max_iter must be >= 1");
     if (!std::isfinite(P.rtol)) return fail(SEM_ERR_INVALID, "rtol is not finite");
+    if (P.mixed < 0 || P.mixed > 2) return fail(SEM_ERR_INVALID, "mixed must be 0, 1 or 2");
     if (P.mixed) {
         if (!(coef->flags & SEM_COEF_F32)) return fail(SEM_ERR_INVALID, "mixed solve needs a coef created with SEM_COEF_F32");
+        if (P.rtol <= 0) return fail(SEM_ERR_INVALID, "mixed solve needs rtol > 0");
+    }
+    if (P.mixed == 1 && !(P.delta == 0.0 || (P.delta > 0.0 && P.delta < 1.0)))
+        return fail(SEM_ERR_INVALID, "delta must be 0 (default) or in (0, 1)");
+    if (P.mixed == 2) {
         if (!(P.inner_rtol > 0.0 && P.inner_rtol < 1.0)) return fail(SEM_ERR_INVALID, "inner_rtol must be in (0, 1)");
         if (P.inner_max_iter < 1) return fail(SEM_ERR_INVALID, "inner_max_iter must be >= 1");
-        if (P.rtol <= 0) return fail(SEM_ERR_INVALID, "mixed solve needs rtol > 0");
     }
     const size_t bytes = (size_t)coef->n * nfields * 8;
     if (bytes == 0) return SEM_OK;
@@ -1166,7 +1334,8 @@ sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef,
     SEM_TRY(gs_upload(gs));
     SEM_TRY(ensure_dinv(coef, gs, st));
     SEM_TRY(ensure_work(coef, nfields, P.mixed != 0));
-    if (P.mixed) return pcg_mixed(x, b, nfields, coef, gs, &P, info, st);
+    if (P.mixed == 1) return pcg_mixed_reliable(x, b, nfields, coef, gs, &P, info, st);
+    if (P.mixed == 2) return pcg_mixed(x, b, nfields, coef, gs, &P, info, st);
     return pcg_fp64(x, b, nfields, coef, gs, &P, info, st);
 }
 

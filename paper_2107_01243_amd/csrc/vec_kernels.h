@@ -70,6 +70,31 @@ struct CgFinishArgs {
     int nfields;
 };
 
+// Per-field state of the reliable-update mixed solve (device resident).
+struct RelState {
+    double bb64;   // (b, b) of the FP64 system
+    double rr64;   // (r, r) of the latest FP64 true residual
+    double tol;    // FP64 relative residual target
+    double delta;  // FP32 segment: reduce the residual by this factor, then replace it
+    int done;      // 1: converged (or failed) -- no further segments
+    int outer;     // residual replacements performed
+};
+
+// r32 = (float) r64, x32 = 0 (optionally p32 = 0), partials of (r32, dinv r32),
+// (r32, r32) and (r64, r64) over owned points, for fields not done.
+struct RelRestartArgs {
+    const double *r64;
+    float *r32;
+    float *x32;
+    float *p32;        // zeroed when non-null (first segment)
+    const float *dinv32;
+    const uint8_t *owner;
+    const RelState *rel;
+    double *partial;   // [3][field][grid]
+    int64_t n;
+    int nfields;
+};
+
 struct DotArgs {
     const double *a[4];
     const double *b[4];

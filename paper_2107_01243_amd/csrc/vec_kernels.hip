@@ -351,6 +351,177 @@ __global__ __launch_bounds__(RT) void k_cg_finish(CgFinishArgs A)
     }
 }
 
+// ------------------------------------------------------------------ reliable-update mixed CG
+// Restart data for a new FP32 segment from the FP64 true residual r64.
+__global__ __launch_bounds__(VT) void k_rel_restart(RelRestartArgs A)
+{
+    __shared__ double sh[3][VT];
+    const int f = blockIdx.y;
+    double rz = 0.0, rr = 0.0, r64 = 0.0;
+    if (!A.rel[f].done) {
+        const double *rs = A.r64 + f * A.n;
+        float *r = A.r32 + f * A.n;
+        float *x = A.x32 + f * A.n;
+        float *p = A.p32 ? A.p32 + f * A.n : nullptr;
+        for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min(A.n, (int64_t)(blockIdx.x + 1) * CHUNK);
+             t < t_end; t += VT) {
+            const double rd = rs[t];
+            const float ri = (float)rd;
+            r[t] = ri;
+            x[t] = 0.0f;
+            if (p) p[t] = 0.0f;
+            if (A.owner[t]) {
+                rz += (double)ri * (double)(A.dinv32[t] * ri);
+                rr += (double)ri * (double)ri;
+                r64 += rd * rd;
+            }
+        }
+    }
+    sh[0][threadIdx.x] = rz;
+    sh[1][threadIdx.x] = rr;
+    sh[2][threadIdx.x] = r64;
+    __syncthreads();
+    for (int s = VT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) A.partial[((int64_t)q * A.nfields + f) * gridDim.x + blockIdx.x] = sh[q][0];
+}
+
+// Start (first = 1) or resume an FP32 segment after a residual replacement.  The
+// FP64 true residual decides convergence.  Resuming keeps the search direction p:
+// beta is rescaled to the replaced residual, beta = (r_new, z_new) / (r_old, z_old).
+// The segment stops once its residual has dropped by max(delta, half of the
+// reduction still needed), at most 0.5.
+__global__ __launch_bounds__(RT) void k_rel_resume(CgFinishArgs F, RelState *rel, int first)
+{
+    __shared__ double sh[RT];
+    for (int f = 0; f < F.nfields; ++f) {
+        const double rz = block_sum_fixed<RT>(F.partial + (0 * F.nfields + f) * F.nblk, F.nblk, sh);
+        const double rr = block_sum_fixed<RT>(F.partial + (1 * F.nfields + f) * F.nblk, F.nblk, sh);
+        const double r64 = block_sum_fixed<RT>(F.partial + (2 * F.nfields + f) * F.nblk, F.nblk, sh);
+        if (threadIdx.x == 0) {
+            RelState &R = rel[f];
+            CgScalars &s = F.scal[f];
+            if (R.done) continue;
+            R.rr64 = r64;
+            R.outer += first ? 0 : 1;
+            // the segment that just ended failed (breakdown) or used up the iterations
+            if (!first && s.status != 0) {
+                R.done = 1;
+                s.stop = 1;
+                continue;
+            }
+            const double rel64 = R.bb64 > 0.0 ? sqrt(r64 / R.bb64) : 0.0;
+            if (!isfinite(r64) || !isfinite(rz)) {
+                R.done = 1;
+                s.stop = 1;
+                s.status = 2;
+                continue;
+            }
+            if (R.bb64 == 0.0 || rel64 <= R.tol) {
+                R.done = 1;
+                s.stop = 1;
+                s.status = 0;
+                continue;
+            }
+            if (first) {
+                s.beta = 0.0;
+                s.iter = 0;
+            } else {
+                s.beta = (s.rz != 0.0) ? s.beta * (rz / s.rz) : 0.0;
+            }
+            s.rz = rz;
+            s.rr = rr;
+            s.bb = rr;  // the segment's reference residual
+            const double need = R.tol / rel64;
+            s.rtol = fmin(0.5, fmax(R.delta, 0.5 * need));
+            s.alpha = 0.0;
+            s.status = 0;
+            s.stop = 0;
+            if (s.iter >= s.max_iter) {
+                s.stop = 1;
+                s.status = 1;
+                R.done = 1;
+            }
+        }
+    }
+}
+
+// Residual replacement for a CG in precision T: partials of (r, dinv r) and (r, r)
+// for a freshly recomputed residual r, on fields flagged in `redo`.
+template <typename T>
+__global__ __launch_bounds__(VT) void k_cg_replace(const T *r_all, const T *dinv, const uint8_t *owner,
+                                                   const int *redo, double *partial, int64_t n, int nfields)
+{
+    __shared__ double sh[2][VT];
+    const int f = blockIdx.y;
+    double rz = 0.0, rr = 0.0;
+    if (redo[f]) {
+        const T *r = r_all + f * n;
+        for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min(n, (int64_t)(blockIdx.x + 1) * CHUNK);
+             t < t_end; t += VT) {
+            if (owner[t]) {
+                const T ri = r[t];
+                rz += (double)ri * (double)(dinv[t] * ri);
+                rr += (double)ri * (double)ri;
+            }
+        }
+    }
+    sh[0][threadIdx.x] = rz;
+    sh[1][threadIdx.x] = rr;
+    __syncthreads();
+    for (int s = VT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 2; ++q) partial[((int64_t)q * nfields + f) * gridDim.x + blockIdx.x] = sh[q][0];
+}
+
+// Resume the CG of the fields flagged in `redo` after their residual was replaced:
+// beta rescaled to the replaced residual, recursive norms reset, iteration continues
+// (unless the iteration cap is reached).
+__global__ __launch_bounds__(RT) void k_cg_resume(CgFinishArgs F, const int *redo)
+{
+    __shared__ double sh[RT];
+    for (int f = 0; f < F.nfields; ++f) {
+        const double rz = block_sum_fixed<RT>(F.partial + (0 * F.nfields + f) * F.nblk, F.nblk, sh);
+        const double rr = block_sum_fixed<RT>(F.partial + (1 * F.nfields + f) * F.nblk, F.nblk, sh);
+        if (threadIdx.x == 0 && redo[f]) {
+            CgScalars &s = F.scal[f];
+            s.beta = (s.rz != 0.0) ? s.beta * (rz / s.rz) : 0.0;
+            s.rz = rz;
+            s.rr = rr;
+            if (!isfinite(rz) || !isfinite(rr)) {
+                s.stop = 1;
+                s.status = 2;
+            } else if (s.iter >= s.max_iter) {
+                s.stop = 1;
+                s.status = 1;
+            } else {
+                s.stop = 0;
+                s.status = 0;
+            }
+        }
+    }
+}
+
+// x64 += (double) x32 on fields not done before this segment (done_before[f] == 0).
+__global__ __launch_bounds__(VT) void k_add_f32(double *x64, const float *x32, const int *skip, int64_t n)
+{
+    const int f = blockIdx.y;
+    if (skip[f]) return;
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x, t_end = min(n, (int64_t)(blockIdx.x + 1) * CHUNK);
+         t < t_end; t += VT)
+        x64[f * n + t] += (double)x32[f * n + t];
+}
+
 // ------------------------------------------------------------------ generic dots
 // partial[q][f][block] for q in 0..nd-1: sum over owned points of a_q * b_q (FP64).
 __global__ __launch_bounds__(VT) void k_dots(DotArgs A)
@@ -557,6 +728,34 @@ hipError_t sem_launch_cg_update_f32(const CgUpdateArgs<float> *A, unsigned grid,
 hipError_t sem_launch_cg_finish(const CgFinishArgs *A, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(RT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_rel_restart(const RelRestartArgs *A, unsigned grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rel_restart, dim3(grid, A->nfields), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_rel_resume(const CgFinishArgs *F, RelState *rel, int first, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rel_resume, dim3(1), dim3(RT), 0, st, *F, rel, first);
+    return hipGetLastError();
+}
+hipError_t sem_launch_add_f32(double *x64, const float *x32, const int *skip, int64_t n, int nfields,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(k_add_f32, dim3(stream_grid(n), nfields), dim3(VT), 0, st, x64, x32, skip, n);
+    return hipGetLastError();
+}
+hipError_t sem_launch_cg_replace_f64(const double *r, const double *dinv, const uint8_t *owner, const int *redo,
+                                     double *partial, int64_t n, int nfields, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_replace<double>, dim3(stream_grid(n), nfields), dim3(VT), 0, st, r, dinv, owner, redo,
+                       partial, n, nfields);
+    return hipGetLastError();
+}
+hipError_t sem_launch_cg_resume(const CgFinishArgs *F, const int *redo, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_resume, dim3(1), dim3(RT), 0, st, *F, redo);
     return hipGetLastError();
 }
 hipError_t sem_launch_dots(const DotArgs *A, unsigned grid, hipStream_t st)
