@@ -181,7 +181,7 @@ def main():
             t1 = time.perf_counter()
             x.zero_()
             infom = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, mixed="reliable",
-                                  check_every=25)
+                                  check_every=10)
             torch.cuda.synchronize()
             tm = time.perf_counter() - t1
             t1 = time.perf_counter()

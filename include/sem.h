@@ -190,7 +190,10 @@ typedef struct {
                            0.5)                                                          */
     int inner_max_iter; /* mixed: iteration cap of each inner solve                    */
     int use_x0;         /* 1: x holds the initial guess on entry; 0: start from 0      */
-    double delta;       /* mixed == 1: residual-replacement factor in (0, 1); 0 -> 0.5 */
+    double delta;       /* mixed == 1: residual-replacement factor in (0, 1); 0 -> 0.5.
+                           A segment shorter than 8 iterations squares it for the
+                           next one (floor 1e-3), so fast-converging systems are not
+                           replaced every iteration.                                */
 } sem_pcg_params;
 
 typedef struct {

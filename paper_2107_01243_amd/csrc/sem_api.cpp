@@ -1090,7 +1090,7 @@ static sem_status pcg_mixed_reliable(double *x, const double *b, int nf, sem_coe
     }
     const double delta = (P->delta > 0.0 && P->delta < 1.0) ? P->delta : 0.5;
     for (int f = 0; f < nf; ++f) {
-        W.h_rel[f] = RelState{bb[f], 0.0, P->rtol, delta, 0, 0};
+        W.h_rel[f] = RelState{bb[f], 0.0, P->rtol, delta, 0, 0, 0};
         CgScalars s{};
         s.max_iter = P->max_iter;
         W.h_scal[f] = s;

@@ -78,6 +78,7 @@ struct RelState {
     double delta;  // FP32 segment: reduce the residual by this factor, then replace it
     int done;      // 1: converged (or failed) -- no further segments
     int outer;     // residual replacements performed
+    int last_iter; // iteration count at the latest replacement
 };
 
 // r32 = (float) r64, x32 = 0 (optionally p32 = 0), partials of (r32, dinv r32),

@@ -432,7 +432,11 @@ __global__ __launch_bounds__(RT) void k_rel_resume(CgFinishArgs F, RelState *rel
                 s.iter = 0;
             } else {
                 s.beta = (s.rz != 0.0) ? s.beta * (rz / s.rz) : 0.0;
+                // a fast-converging system reaches delta within a few iterations:
+                // ask for more reduction per segment so replacements stay rare
+                if (s.iter - R.last_iter < 8) R.delta = fmax(R.delta * R.delta, 1e-3);
             }
+            R.last_iter = s.iter;
             s.rz = rz;
             s.rr = rr;
             s.bb = rr;  // the segment's reference residual

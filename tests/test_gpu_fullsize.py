@@ -63,7 +63,7 @@ def test_64cubed_lx8_mixed_vs_fp64():
     torch.cuda.empty_cache()
     timed_solve(P, b, rtol=1e-4, max_iter=50, raise_on_fail=False)       # warm-up
     x64, i64, t64 = timed_solve(P, b, rtol=wl.rtol, check_every=50)
-    xm, im, tm = timed_solve(P, b, rtol=wl.rtol, mixed="reliable", check_every=25)
+    xm, im, tm = timed_solve(P, b, rtol=wl.rtol, mixed="reliable", check_every=10)
     xf, iff, tf = timed_solve(P, b, rtol=wl.rtol, mixed="fcg", inner_rtol=1e-4, inner_max_iter=20000,
                               check_every=50)
     say(f"   fp64: {t64:.3f}s {i64[0]['iters']} it; mixed (reliable updates): {tm:.3f}s "
@@ -100,7 +100,7 @@ def test_48cubed_lx12_three_fields_and_gradient():
     n = P.n
     bl = np.concatenate([workloads.uniform(n, s) for s in workloads.SEED_RHS_FIELDS])
     b = P.assemble(torch.from_numpy(bl).cuda(), nfields=3)
-    x3, info, t = timed_solve(P, b, nfields=3, rtol=wl.rtol, mixed="reliable", check_every=25)
+    x3, info, t = timed_solve(P, b, nfields=3, rtol=wl.rtol, mixed="reliable", check_every=10)
     say(f"   batched mixed solve {t:.3f}s: " + ", ".join(f"{d['iters']}/{d['inner_iters']}" for d in info))
     X3 = x3.view(3, -1).cpu().numpy()
     # gradient on the x component, FP64 forward and adjoint solves
