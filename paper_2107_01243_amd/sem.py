@@ -145,7 +145,8 @@ class Space:
         _check(_L.sem_space_get(h, _np_ptr(self.xi), _np_ptr(self.w), _np_ptr(self.D)))
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "_h", None) and _L is not None:
             _L.sem_space_destroy(self._h)
             self._h = None
 
@@ -180,7 +181,8 @@ class Mesh:
                     n_dirichlet_local=v[4].value)
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "_h", None) and _L is not None:
             _L.sem_mesh_destroy(self._h)
             self._h = None
 
@@ -215,7 +217,8 @@ class GS:
         return u
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "_h", None) and _L is not None:
             _L.sem_gs_destroy(self._h)
             self._h = None
 
@@ -262,7 +265,8 @@ class Coef:
         return G, B
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "_h", None) and _L is not None:
             _L.sem_coef_destroy(self._h)
             self._h = None
 
