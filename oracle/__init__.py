@@ -6,6 +6,10 @@ It shares no code with the HIP path.  The arithmetic lives in
 ``sem_oracle.c`` (plain loops, FP64, ``-O2 -ffp-contract=off``); this module
 only marshals numpy arrays into it.
 
+The projection onto previous solutions (``Problem.projection``) is written
+here with numpy on top of the C operator: a small dense Gram system solved by
+``numpy.linalg.solve``.
+
 Every function cites the passage of the paper it follows; the readings taken
 where the paper is silent or garbled are listed at the top of ``sem_oracle.c``.
 """
@@ -297,6 +301,24 @@ class Problem:
 
     def dot(self, a, b):
         return wdot(a, b, self.mult)
+
+    def projection(self, X, b):
+        """Initial guess from previous solutions (Section 4 and Table 2: the pressure
+        solve keeps a space of previous solutions, after Nek5000).  Definition: the
+        best approximation of A^{-1} b from span(X) in the A-norm, x0 = sum_i c_i X_i
+        with (X^T A X) c = X^T b in the unique-node inner product -- equivalently the
+        Galerkin condition (X_i, b - A x0) = 0.  Returns (x0, r = b - A x0)."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        if len(X) == 0:
+            return np.zeros(self.n), b.copy()
+        AX = [self.apply(x) for x in X]
+        G = np.array([[self.dot(xi, axj) for axj in AX] for xi in X])
+        rhs = np.array([self.dot(xi, b) for xi in X])
+        c = np.linalg.solve(G, rhs)
+        x0 = np.zeros(self.n)
+        for ci, xi in zip(c, X):
+            x0 += ci * xi
+        return x0, b - self.apply(x0)
 
     def true_rel_res(self, x, b):
         r = b - self.apply(x)

@@ -423,3 +423,53 @@ def test_gradient_vs_dense_finite_differences():
         e[p] = 1e-6 * h1[p]
         fd = (loss(h1 + e) - loss(h1 - e)) / (2e-6 * h1[p])
         assert abs(fd - grad[p]) <= 1e-6 * np.abs(grad).max(), (p, fd, grad[p])
+
+
+# ------------------------------------------------------------------ projection (Section 4, Table 2)
+def _proj_case():
+    P = oracle.Problem(2, 5, 0.05)
+    X = []
+    for sd in (21, 22, 23):
+        xs, info = P.pcg(P.assemble_rhs(workloads.uniform(P.n, sd)), rtol=1e-13)
+        assert info["status"] == 0
+        X.append(xs)
+    b = P.assemble_rhs(workloads.uniform(P.n, 24))
+    return P, X, b
+
+
+def test_projection_galerkin_and_exact_recovery():
+    """The residual of the projected guess is orthogonal to every stored solution;
+    a load whose solution lies in the space is solved exactly; an empty space gives 0."""
+    P, X, b = _proj_case()
+    x0, r = P.projection(X, b)
+    bn = np.sqrt(P.dot(b, b))
+    for xi in X:
+        assert abs(P.dot(xi, r)) <= 1e-12 * bn * np.sqrt(P.dot(xi, xi))
+    x0e, re = P.projection(X, P.apply(X[1]))
+    assert np.abs(x0e - X[1]).max() <= 1e-10 * np.abs(X[1]).max()
+    assert np.sqrt(P.dot(re, re)) <= 1e-10 * np.sqrt(P.dot(P.apply(X[1]), P.apply(X[1])))
+    z, rz = P.projection([], b)
+    assert not z.any() and np.array_equal(rz, b)
+
+
+def test_projection_matches_dense_and_is_optimal():
+    """Against an independent dense assembly on the free unique nodes: the same
+    x0 = X (X^T A X)^{-1} X^T b, and no other combination of the stored solutions
+    is closer to A^{-1} b in the A-norm."""
+    P, X, b = _proj_case()
+    x0, _ = P.projection(X, b)
+    A, pos, _, _ = brute.assembled(2, 5, 0.05)
+    p_loc = pos[P.glb]
+    free = p_loc >= 0
+    rep = np.array([np.flatnonzero(p_loc == j)[0] for j in range(A.shape[0])])
+    Xd = np.stack([x[rep] for x in X], axis=1)
+    bd = b[rep]
+    cd = np.linalg.solve(Xd.T @ A @ Xd, Xd.T @ bd)
+    x0d = Xd @ cd
+    np.testing.assert_allclose(x0[free], x0d[p_loc[free]], rtol=0, atol=1e-11 * np.abs(x0d).max())
+    xs = np.linalg.solve(A, bd)
+    e0 = (xs - x0d) @ A @ (xs - x0d)
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        y = Xd @ (cd + 0.1 * rng.standard_normal(len(X)) * np.abs(cd).max())
+        assert (xs - y) @ A @ (xs - y) >= e0
