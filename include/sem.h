@@ -63,6 +63,7 @@ typedef struct sem_space_s *sem_space; /* Xh: lx, GLL points/weights, D (Eq. 7-9
 typedef struct sem_mesh_s *sem_mesh;   /* msh: nelv, lx, global ids, Dirichlet mask  */
 typedef struct sem_coef_s *sem_coef;   /* coef: G, B, h1, h2, Jacobi cache            */
 typedef struct sem_gs_s *sem_gs;       /* gs: pair list + block lists for QQ^T        */
+typedef struct sem_proj_s *sem_proj;   /* proj: previous-solution projection space    */
 
 /* Flag for sem_coef_create*: also keep FP32 copies of G, B, D (needed by SEM_F32
  * calls and by the mixed-precision solve). */
@@ -213,6 +214,39 @@ typedef struct {
 sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef, sem_mesh msh,
                          sem_space Xh, sem_gs gs, const sem_pcg_params *params,
                          sem_pcg_info *info, void *stream);
+
+/* ---------------------------------------------------------------- projection space
+ * Initial guesses from previous solutions (the paper keeps a space of 20 previous
+ * pressure solutions, Section 4 and Table 2, following Nek5000).  The handle holds
+ * up to max_vectors A-orthonormal vectors X_i, (X_i, A X_j) = delta_ij in the
+ * unique-node inner product, and their images A X_i, for the operator of coef
+ * (A = mask QQ^T A_L(h1, h2)) on one scalar field: 2 * max_vectors * n_p FP64
+ * values of device memory plus four scratch vectors, owned by the handle.
+ * The operator must not change while the space is in use: call sem_proj_reset
+ * after changing h1 or h2.  The handle keeps pointers to coef, msh, Xh and gs,
+ * which must outlive it.  Not thread-safe; calls are ordered on `stream`. */
+sem_status sem_proj_create(sem_coef coef, sem_mesh msh, sem_space Xh, sem_gs gs, int max_vectors,
+                           sem_proj *proj);
+sem_status sem_proj_size(sem_proj proj, int *count, int *max_vectors, int *restarts);
+sem_status sem_proj_reset(sem_proj proj);
+/* x0 = sum_i (X_i, b) X_i, the best approximation of A^{-1} b from the space in the
+ * A-norm (equivalently (X_i, b - A x0) = 0 for every i), and r = b - A x0 computed
+ * from the stored images.  b assembled and masked; x0, r, b device FP64 (n_p values),
+ * pairwise non-overlapping.  An empty space gives x0 = 0, r = b. */
+sem_status sem_proj_project(sem_proj proj, double *x0, double *r, const double *b, void *stream);
+/* Add the solution x of a system whose projection was x0: the new direction x - x0
+ * is A-orthogonalised against the space (classical Gram-Schmidt, two passes, one
+ * operator application) and appended unless it is dependent to rounding (*added = 0).
+ * A full space restarts from x alone (counted in restarts). */
+sem_status sem_proj_update(sem_proj proj, const double *x, const double *x0, int *added, void *stream);
+/* Project, solve A dx = b - A x0 with sem_pcg_solve (params as there, rtol > 0,
+ * relative to |b|: the correction solve stops once |b - A x| <= rtol |b|), set
+ * x = x0 + dx, add x to the space.  info: iters / inner_iters of the correction
+ * solve, rel_res and true_rel_res relative to |b|.  Returns what the correction
+ * solve returned (SEM_ERR_NOT_CONVERGED with x valid). */
+sem_status sem_proj_solve(double *x, const double *b, sem_proj proj, const sem_pcg_params *params,
+                          sem_pcg_info *info, void *stream);
+void sem_proj_destroy(sem_proj proj);
 
 /* ---------------------------------------------------------------- measurement
  * STREAM triad a = b + s*c over n FP64 values (device, caller-owned, a must not

@@ -1,13 +1,14 @@
 """MI355X (gfx950) spectral-element Helmholtz hot path (arXiv 2107.01243, Neko).
 
 Python surface over libsem.so: the operator ax_helm (Eq. 9), gather-scatter
-gs_op (Eq. 10 / Algorithm 1), Jacobi-PCG and FP32/FP64 mixed flexible CG
-(Section 4, Section 10), and the h1-adjoint behind torch.autograd.
+gs_op (Eq. 10 / Algorithm 1), Jacobi-PCG with FP64 or FP32/FP64 mixed precision
+(Section 4, Section 10), projection onto previous solutions (Section 4,
+Table 2), and the h1-adjoint behind torch.autograd.
 """
-from .sem import (BoxProblem, Coef, GS, Mesh, PcgInfo, PcgParams, SemError, Space, ax_helm,
-                  ax_helm_adjoint, box_mesh, jacobi_inverse, lib, mask, pcg_solve)
+from .sem import (BoxProblem, Coef, GS, Mesh, PcgInfo, PcgParams, Projection, SemError, Space, ax_helm,
+                  ax_helm_adjoint, box_mesh, jacobi_inverse, lib, mask, pcg_solve, stream_triad)
 from .autograd import HelmholtzSolve
 
-__all__ = ["BoxProblem", "Coef", "GS", "Mesh", "PcgInfo", "PcgParams", "SemError", "Space",
+__all__ = ["BoxProblem", "Coef", "GS", "Mesh", "PcgInfo", "PcgParams", "Projection", "SemError", "Space",
            "ax_helm", "ax_helm_adjoint", "box_mesh", "jacobi_inverse", "lib", "mask", "pcg_solve",
-           "HelmholtzSolve"]
+           "stream_triad", "HelmholtzSolve"]

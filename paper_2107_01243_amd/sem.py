@@ -70,6 +70,13 @@ _SIGS = {
     "sem_pcg_solve": ([_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.POINTER(PcgParams),
                        C.POINTER(PcgInfo), _vp], C.c_int),
     "sem_stream_triad": ([_vp, _vp, _vp, C.c_double, C.c_int64, _vp], C.c_int),
+    "sem_proj_create": ([_vp, _vp, _vp, _vp, C.c_int, C.POINTER(_vp)], C.c_int),
+    "sem_proj_size": ([_vp, _vp, _vp, _vp], C.c_int),
+    "sem_proj_reset": ([_vp], C.c_int),
+    "sem_proj_project": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
+    "sem_proj_update": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
+    "sem_proj_solve": ([_vp, _vp, _vp, C.POINTER(PcgParams), C.POINTER(PcgInfo), _vp], C.c_int),
+    "sem_proj_destroy": ([_vp], None),
     "sem_last_error": ([], C.c_char_p),
     "sem_version": ([], C.c_char_p),
 }
@@ -330,6 +337,65 @@ def pcg_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, nfields: int = 1, 
     return out
 
 
+class Projection:
+    """Space of up to max_vectors previous solutions of one scalar system, used for
+    initial guesses (Section 4 and Table 2: 20 previous pressure solutions)."""
+
+    def __init__(self, coef: Coef, msh: Mesh, Xh: Space, gs: GS, max_vectors: int = 20):
+        h = _vp()
+        _check(_L.sem_proj_create(coef._h, msh._h, Xh._h, gs._h, int(max_vectors), C.byref(h)))
+        self._h = h
+        self._keep = (coef, msh, Xh, gs)   # the handle points at these
+        self.n = msh.n
+
+    def __del__(self):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "_h", None) and _L is not None:
+            _L.sem_proj_destroy(self._h)
+            self._h = None
+
+    def size(self):
+        """(vectors held, capacity, restarts)."""
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        _check(_L.sem_proj_size(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def reset(self):
+        _check(_L.sem_proj_reset(self._h))
+
+    def project(self, b, stream=None):
+        """(x0, r = b - A x0): best A-norm approximation of A^{-1} b from the space."""
+        _dev(b, self.n, "b")
+        x0 = torch.empty_like(b)
+        r = torch.empty_like(b)
+        _check(_L.sem_proj_project(self._h, _ptr(x0), _ptr(r), _ptr(b), _stream(stream)))
+        return x0, r
+
+    def update(self, x, x0, stream=None) -> bool:
+        """Add the solution x (whose projection was x0); False if it added nothing."""
+        _dev(x, self.n, "x")
+        _dev(x0, self.n, "x0")
+        added = C.c_int()
+        _check(_L.sem_proj_update(self._h, _ptr(x), _ptr(x0), C.byref(added), _stream(stream)))
+        return bool(added.value)
+
+    def solve(self, b, rtol: float = 1e-10, max_iter: int = 100000, check_every: int = 25, mixed=False,
+              inner_rtol: float = 1e-4, inner_max_iter: int = 2000, delta: float = 0.5, stream=None,
+              raise_on_fail: bool = True):
+        """x = x0 + dx with A dx = b - A x0 solved by PCG; x joins the space."""
+        _dev(b, self.n, "b")
+        x = torch.empty_like(b)
+        P = PcgParams(float(rtol), int(max_iter), int(check_every), MIXED_MODES[mixed], float(inner_rtol),
+                      int(inner_max_iter), 0, float(delta))
+        info = PcgInfo()
+        st = _L.sem_proj_solve(_ptr(x), _ptr(b), self._h, C.byref(P), C.byref(info), _stream(stream))
+        d = info.as_dict()
+        d["status"] = st
+        if st != SEM_OK and raise_on_fail:
+            raise SemError(st, _L.sem_last_error().decode(errors="replace"))
+        return x, d
+
+
 def stream_triad(a, b, c, s: float, stream=None):
     """a = b + s c (FP64 device vectors): the STREAM-triad bandwidth probe."""
     for t, nm in ((a, "a"), (b, "b"), (c, "c")):
@@ -394,3 +460,6 @@ class BoxProblem:
     def adjoint(self, u, v):
         g = torch.empty_like(u)
         return ax_helm_adjoint(g, u, v, self.coef, self.msh, self.Xh)
+
+    def projection(self, max_vectors: int = 20) -> Projection:
+        return Projection(self.coef, self.msh, self.Xh, self.gs, max_vectors)

@@ -321,6 +321,81 @@ def test_mixed_three_fields_lx12(mode):
     P.coef.set_helmholtz(1.0, 0.0)
 
 
+# ------------------------------------------------------------------ projection (Section 4, Table 2)
+def test_projection_sequence_vs_oracle():
+    """A sequence of slowly varying loads (two fixed patterns plus 1e-6 noise) solved
+    with a space of at most three previous solutions: every projected guess x0 and
+    residual r against the oracle's best A-norm approximation from its own stored
+    solutions; the correction solve's iteration count against the oracle's PCG from
+    the same guess; the restart when the space is full; the iteration savings."""
+    say("[projection sequence]")
+    P, O = pair(5, 6)
+    P.coef.set_helmholtz(1.0, 0.0)
+    O.set_coef(1.0, 0.0)
+    m = 3
+    proj = P.projection(m)
+    assert proj.size() == (0, m, 0)
+    L, its = [], []
+    for k in range(7):
+        fl = workloads.sequence_load(P.n, k, modes=2)
+        bo = O.assemble_rhs(fl)
+        b = P.assemble(to_dev(fl))
+        x0, r = proj.project(b)
+        x0o, ro = O.projection(L, bo)
+        if L:
+            assert rel_inf(host(x0), x0o) <= 1e-8
+        else:
+            assert not host(x0).any()
+        assert np.abs(host(r) - ro).max() <= 1e-8 * np.abs(bo).max()
+        x, info = proj.solve(b, rtol=1e-12)
+        xo, io = O.pcg(bo, x0=x0o, rtol=1e-12)
+        say(f"   step {k}: space {len(L)}, iterations {info['iters']} (oracle {io['iters']}), "
+            f"size {proj.size()}")
+        assert abs(info["iters"] - io["iters"]) <= max(2, math.ceil(0.01 * io["iters"]))
+        assert rel_inf(host(x), xo) <= 1e-8
+        assert O.true_rel_res(host(x), bo) <= 1.05e-12
+        assert abs(info["true_rel_res"] - O.true_rel_res(host(x), bo)) <= 1e-2 * 1e-12 + 1e-3 * info["true_rel_res"]
+        its.append(info["iters"])
+        L = [xo] if len(L) == m else L + [xo]
+    assert proj.size() == (1, m, 2)   # restarted after the 4th and the 7th solve
+    for k in (2, 3, 5, 6):
+        assert its[k] <= 0.65 * its[0], its
+    # a solution already in the space adds nothing; reset empties the space
+    x0, _ = proj.project(b)
+    assert not proj.update(x0, x0)
+    proj.reset()
+    assert proj.size() == (0, m, 0)
+
+
+def test_projection_full_size_32cubed_lx8():
+    """The projected sequence at 32^3 x lx=8 with a 20-vector space: each solution
+    meets 1e-10 on the oracle's own residual, the projected residual is orthogonal
+    to the earlier solutions, and the iteration count drops once the patterns are
+    in the space."""
+    say("[projection full] building 32^3 lx=8")
+    P = sem.BoxProblem.build(32, 8, 0.05)
+    O = oracle.Problem(32, 8, 0.05, progress=say)
+    mult = P.gs.maps()[3].astype(np.float64)
+    dot = lambda a, c: float(np.sum(a * c / mult))
+    proj = P.projection(20)
+    xs, its = [], []
+    for k in range(4):
+        fl = workloads.sequence_load(P.n, k, modes=2)
+        b = P.assemble(to_dev(fl))
+        x0, r = proj.project(b)
+        rh, bh = host(r), host(b)
+        for xp in xs:
+            assert abs(dot(xp, rh)) <= 1e-12 * math.sqrt(dot(xp, xp) * dot(bh, bh))
+        x, info = proj.solve(b, rtol=1e-10, check_every=20)
+        xh = host(x)
+        tr = O.true_rel_res(xh, O.assemble_rhs(fl))
+        say(f"   step {k}: iterations {info['iters']}, oracle true residual {tr:.3e}")
+        assert tr <= 1.2e-10
+        xs.append(xh)
+        its.append(info["iters"])
+    assert its[2] <= 0.7 * its[0] and its[3] <= 0.7 * its[0], its
+
+
 def test_solver_error_paths():
     say("[errors]")
     P, O = pair(3, 8)

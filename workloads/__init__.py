@@ -7,7 +7,8 @@ take their inputs from it without sharing method code.
 
 All random draws use numpy ``Generator(PCG64(seed))``.  Seeds: 0 = operand u,
 1 = right-hand side, 2 and 3 = the two Gaussian-random-field draws,
-11 and 21 = the second and third velocity components' right-hand sides.
+11 and 21 = the second and third velocity components' right-hand sides,
+31.. = the fixed patterns and 131.. = the per-step noise of a load sequence.
 
 The paper's own workloads (Taylor-Green vortex, pipe, hemisphere meshes and DNS
 data) are not available; these box meshes stand in for them with the same
@@ -73,6 +74,7 @@ WORKLOADS = {
 # seeds
 SEED_U, SEED_RHS, SEED_GRF, SEED_GRF_TARGET = 0, 1, 2, 3
 SEED_RHS_FIELDS = (1, 11, 21)
+SEED_SEQ, SEED_SEQ_NOISE = 31, 131
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -119,3 +121,17 @@ def sine_source(x, y, z):
 
 def sine_exact(x, y, z):
     return np.sin(math.pi * x) * np.sin(math.pi * y) * np.sin(math.pi * z)
+
+
+def sequence_load(n: int, k: int, modes: int = 4, dt: float = 0.05, noise: float = 1e-6) -> np.ndarray:
+    """Local load vector of step k of a slowly varying sequence, standing in for the
+    successive pressure right-hand sides of a time-stepping run: `modes` fixed U[-1,1]
+    patterns (seeds SEED_SEQ + j) with amplitudes 1 + 0.5 cos(w_j k dt + j), plus U[-1,1]
+    noise of size `noise` drawn afresh each step (seed SEED_SEQ_NOISE + k)."""
+    omega = (1.0, 1.7, 2.3, 3.1, 3.7, 4.3, 5.1, 5.9)
+    f = np.zeros(n)
+    for j in range(modes):
+        f += (1.0 + 0.5 * math.cos(omega[j % len(omega)] * k * dt + j)) * uniform(n, SEED_SEQ + j)
+    if noise:
+        f += noise * uniform(n, SEED_SEQ_NOISE + k)
+    return f
