@@ -13,7 +13,9 @@ One step = the whole hot path once:
 value = FP64 ax_helm GDOF/s = n_p / (average ax_helm launch time), from HIP events
 on the launch stream over the timed steps.  The JSON line also carries both solve
 times, iteration counts, the roofline of the ax_helm kernel and the CPU oracle
-baseline.
+baseline.  After the timed steps (not part of ms_per_step) a sequence of slowly
+varying loads is solved with a 20-vector projection space (initial guesses from
+previous solutions) and its per-solve iterations and times are reported.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -96,11 +98,15 @@ def main():
     ap.add_argument("--reps", type=int, default=20, help="ax_helm launches per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--proj-steps", type=int, default=8,
+                    help="solves of the slowly varying load sequence with a 20-vector projection space "
+                         "(0: skip)")
     ap.add_argument("--inner-rtol", type=float, default=1e-4, dest="inner_rtol",
                     help="nominal inner tolerance of the mixed solve")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one plain device copy of 2^27 doubles (reference "
-                         "for counter scaling), --reps ax_helm launches, one gs_op and 20 PCG iterations")
+                         "for counter scaling), --reps ax_helm launches, one gs_op, 20 PCG iterations "
+                         "and nine projection-space updates")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the multi-GPU path "
@@ -158,6 +164,12 @@ def main():
         x.zero_()
         sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-10, mixed="reliable", max_iter=20,
                       check_every=20, raise_on_fail=False)
+        # projection-space kernels: fill eight vectors, then one projection with l = 8
+        proj = P.projection(20)
+        for k in range(9):
+            v = P.assemble(torch.from_numpy(workloads.uniform(P.n, 40 + k)).cuda())
+            x0, _ = proj.project(v)
+            proj.update(v, x0)
         torch.cuda.synchronize()
         log("profile pass done")
         return
@@ -245,6 +257,22 @@ def main():
     cold_s = ax_cold()
     log(f"ax cold-cache {cold_s * 1e6:.1f} us/launch")
 
+    # projection onto previous solutions: a sequence of slowly varying loads (four
+    # fixed patterns with drifting amplitudes, 1e-6 noise), FP64 solves to 1e-10 with a
+    # space of 20 previous solutions; the first solve starts from an empty space
+    proj_rec = []
+    if a.proj_steps > 0:
+        proj = P.projection(20)
+        for k in range(a.proj_steps):
+            bk = P.assemble(torch.from_numpy(workloads.sequence_load(P.n, k, modes=4)).cuda())
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, pinfo = proj.solve(bk, rtol=wl.rtol, check_every=50)
+            torch.cuda.synchronize()
+            proj_rec.append((time.perf_counter() - t1, pinfo["iters"], pinfo["true_rel_res"]))
+            log(f"projected solve {k + 1}/{a.proj_steps}: {proj_rec[-1][0]:.3f}s, {pinfo['iters']} it")
+        del proj
+
     traffic = profiled_traffic("sem::k_ax_helm<8, double, 1, false>")
     ax_s = sum(rec["ax_ms"]) / 1e3 / (a.reps * a.steps)
     gdofs = P.n / ax_s / 1e9
@@ -295,6 +323,18 @@ def main():
             "pcg_fcg_outer_iters": int(np.median(rec["fcg_outer"])),
             "pcg_fcg_inner_iters": int(np.median(rec["fcg_inner"])),
             "pcg_fcg_true_rel_res": float(np.max(rec["fcg_tr"])),
+        })
+    out["ax_unique_gdofs"] = round(wl.n_unique / ax_s / 1e9, 3)
+    out["pcg_fp64_gpoint_iters_per_s"] = round(P.n * out["pcg_fp64_iters"] / out["pcg_fp64_solve_s"] / 1e9, 3)
+    if proj_rec:
+        warm = proj_rec[4:] if len(proj_rec) > 4 else proj_rec[-1:]
+        out.update({
+            "proj_space": 20,
+            "proj_sequence": "4 fixed U[-1,1] patterns, amplitudes 1 + 0.5 cos(w_j k dt + j), 1e-6 noise",
+            "proj_iters": [r[1] for r in proj_rec],
+            "proj_solve_s": [round(r[0], 4) for r in proj_rec],
+            "proj_true_rel_res_max": float(max(r[2] for r in proj_rec)),
+            "proj_speedup_after_4": round(proj_rec[0][0] / float(np.mean([r[0] for r in warm])), 3),
         })
     if not a.no_cpu_baseline:
         del P, u, w, x, b
