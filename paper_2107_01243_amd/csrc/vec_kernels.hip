@@ -207,7 +207,9 @@ __global__ __launch_bounds__(VT) void k_mdot(MdotArgs A)
 // Linear combination of up to PB basis vectors (coefficients by value).
 __global__ __launch_bounds__(VT) void k_comb(CombArgs A)
 {
-    // the starting vector is chosen once per launch (uniform): none, y itself, or src
+    // the starting vector is chosen once per launch (uniform): none, y itself, or src.
+    // (Selecting it per point with a nested conditional was compiled, for src, into a
+    // load through a scalar register that was never assigned on that path.)
     const double *s0 = (A.mode == 1) ? A.y : A.src;
     const bool start = A.mode != 0;
     const int64_t t_end = min(A.n, (int64_t)(blockIdx.x + 1) * CHUNK);
