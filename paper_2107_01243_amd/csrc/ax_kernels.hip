@@ -368,6 +368,12 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DE
     const bool act = e < A.nelv;
     const int64_t row = e * (int64_t)(LX * LX * LX) + t;  // base of this lane's t-pencil
     T *s0 = lds.buf[0][slot], *s1 = lds.buf[1][slot];
+    // a launch queued after every field has stopped (between host polls) reads
+    // nothing: the same flags for every lane, so the exit is uniform
+    bool live = false;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) live = live || !A.scal[f].stop;
+    if (!live) return;
 
     T g[6][LX];
 #pragma unroll

@@ -52,6 +52,7 @@ SEM_LX_LIST(SEM_DECL)
 
 extern "C" {
 unsigned sem_vec_grid(int64_t n);
+unsigned sem_update_grid(int64_t n, int f32);
 hipError_t sem_launch_gs_f64(const GsArgs<double> *, hipStream_t);
 hipError_t sem_launch_gs_f32(const GsArgs<float> *, hipStream_t);
 hipError_t sem_launch_mask(void *, int, const int32_t *, int64_t, int64_t, int, hipStream_t);
@@ -449,7 +450,8 @@ sem_status ensure_work(sem_coef c, int nf, bool mixed)
         SEM_TRY(dalloc(&W.ri32, nn));
     }
     const int64_t nb = std::max<int64_t>({fns(c->lx).nblk64(c->nelv), fns(c->lx).nblk32(c->nelv),
-                                          (int64_t)sem_vec_grid(n)});
+                                          (int64_t)sem_vec_grid(n), (int64_t)sem_update_grid(n, 0),
+                                          (int64_t)sem_update_grid(n, 1)});
     W.partial_len = 4 * (int64_t)nf * nb;
     SEM_TRY(dalloc(&W.partial, W.partial_len));
     SEM_TRY(dalloc(&W.scal, nf));
@@ -553,7 +555,7 @@ sem_status cg_iterate(sem_coef c, sem_gs g, int nf, T *x, T *r, T *p, T *w, cons
     Work &W = c->ws;
     const int64_t n = c->n;
     const bool f64 = sizeof(T) == 8;
-    const unsigned vg = sem_vec_grid(n);
+    const unsigned ug = sem_update_grid(n, f64 ? 0 : 1);
     const AlphaJob *job = f64 ? W.job64 : W.job32;
     CgMatvecArgs<T> M;
     M.p = p;
@@ -571,7 +573,7 @@ sem_status cg_iterate(sem_coef c, sem_gs g, int nf, T *x, T *r, T *p, T *w, cons
     M.scal = W.scal;
     M.partial = W.partial;
     CgUpdateArgs<T> U{x, r, p, w, dinv, g->d_owner, W.scal, W.partial, n, nf};
-    CgFinishArgs F{W.partial, (int64_t)vg, W.scal, hist, hist_len, nf};
+    CgFinishArgs F{W.partial, (int64_t)ug, W.scal, hist, hist_len, nf};
     if (check_every < 1) check_every = 1;
     const int64_t max_batches = (int64_t)(max_iter + check_every - 1) / check_every + 2;
     // first poll right after initialisation (b = 0 or an exact initial guess)
@@ -588,8 +590,8 @@ sem_status cg_iterate(sem_coef c, sem_gs g, int nf, T *x, T *r, T *p, T *w, cons
             if constexpr (sizeof(T) == 8) HIP_TRY(fns(c->lx).cg64(&M, c->Xh->D, nf, st));
             else HIP_TRY(fns(c->lx).cg32(&M, c->Xh->D, nf, st));
             SEM_TRY(launch_gs<T>(w, nf, g, W.scal, job, st));
-            if constexpr (sizeof(T) == 8) HIP_TRY(sem_launch_cg_update_f64(&U, vg, st));
-            else HIP_TRY(sem_launch_cg_update_f32(&U, vg, st));
+            if constexpr (sizeof(T) == 8) HIP_TRY(sem_launch_cg_update_f64(&U, ug, st));
+            else HIP_TRY(sem_launch_cg_update_f32(&U, ug, st));
             HIP_TRY(sem_launch_cg_finish(&F, st));
         }
         HIP_TRY(hipMemcpyAsync(W.h_scal, W.scal, sizeof(CgScalars) * nf, hipMemcpyDeviceToHost, st));
@@ -1117,7 +1119,8 @@ static sem_status pcg_mixed_reliable(double *x, const double *b, int nf, sem_coe
     M.scal = W.scal;
     M.partial = W.partial;
     CgUpdateArgs<float> U{W.y32, W.r32, W.p32, W.w32, c->dinv32, g->d_owner, W.scal, W.partial, n, nf};
-    CgFinishArgs F{W.partial, (int64_t)vg, W.scal, nullptr, 0, nf};
+    const unsigned ug = sem_update_grid(n, 1);
+    CgFinishArgs F{W.partial, (int64_t)ug, W.scal, nullptr, 0, nf};
     const int check_every = std::max(1, P->check_every);
     const int64_t max_polls = (int64_t)P->max_iter / check_every + 64 * 64;
     for (int64_t poll = 0; poll < max_polls; ++poll) {
@@ -1145,7 +1148,7 @@ static sem_status pcg_mixed_reliable(double *x, const double *b, int nf, sem_coe
         for (int it = 0; it < check_every; ++it) {
             HIP_TRY(fns(c->lx).cg32(&M, c->Xh->D, nf, st));
             SEM_TRY(launch_gs<float>(W.w32, nf, g, W.scal, W.job32, st));
-            HIP_TRY(sem_launch_cg_update_f32(&U, vg, st));
+            HIP_TRY(sem_launch_cg_update_f32(&U, ug, st));
             HIP_TRY(sem_launch_cg_finish(&F, st));
         }
     }

@@ -35,6 +35,19 @@ constexpr int VCH = SEM_VCH;
 constexpr int64_t CHUNK = (int64_t)VT * VCH;
 constexpr int RT = 1024;  // lanes of the single-workgroup reduction kernels
 
+#ifndef SEM_UPD64
+#define SEM_UPD64 2
+#endif
+#ifndef SEM_UPD32
+#define SEM_UPD32 4
+#endif
+// Points per lane of one CG-update workgroup, per precision: an FP32 chunk moves half
+// the bytes of an FP64 one, so it takes more points to amortise the workgroup's
+// reduction epilogue (and it halves the partials the finish kernel sums).
+template <typename T> struct UpdChunk;
+template <> struct UpdChunk<double> { static constexpr int UV = SEM_UPD64; };
+template <> struct UpdChunk<float> { static constexpr int UV = SEM_UPD32; };
+
 // Sum `nblk` partials in a fixed order inside one workgroup of NTH lanes: lane t
 // accumulates entries t, t+NTH, ... into four interleaved accumulators (loads in
 // flight), combines them, then a fixed binary tree in LDS.  Deterministic for a
@@ -130,6 +143,12 @@ __global__ __launch_bounds__(VT) void k_gs_entries(GsArgs<T> A)
 #else
     const unsigned lb = blockIdx.x;
 #endif
+    if (A.skip) {
+        // every field stopped: nothing to gather, and no step length left to set
+        bool live = false;
+        for (int f = 0; f < A.nfields; ++f) live = live || !A.skip[f].stop;
+        if (!live) return;
+    }
     const int64_t t = (int64_t)lb * VT + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool in = t < A.nent;
@@ -332,10 +351,14 @@ __global__ __launch_bounds__(RT) void k_cg_start(CgFinishArgs A)
 }
 
 // x += alpha p; r -= alpha w (not on Dirichlet points); partials of (r, dinv r), (r, r).
+// Workgroup b streams the contiguous chunk of UV * VT points starting at b * UV * VT
+// (UV per precision: see upd_chunk); its two partials are reduced by wave
+// butterflies and then the four waves in order (deterministic, one barrier).
 template <typename T>
 __global__ __launch_bounds__(VT) void k_cg_update(CgUpdateArgs<T> A)
 {
-    __shared__ double sh[2][VT];
+    constexpr int UV = UpdChunk<T>::UV;
+    __shared__ double sh[2][VT / 64];
     const int f = blockIdx.y;
     const CgScalars &sc = A.scal[f];
     double rz = 0.0, rr = 0.0;
@@ -345,9 +368,10 @@ __global__ __launch_bounds__(VT) void k_cg_update(CgUpdateArgs<T> A)
         T *r = A.r + f * A.n;
         const T *p = A.p + f * A.n;
         const T *w = A.w + f * A.n;
-        const int64_t t_end = min(A.n, (int64_t)(blockIdx.x + 1) * CHUNK);
+        const int64_t t0 = (int64_t)blockIdx.x * UV * VT;
+        const int64_t t_end = min(A.n, t0 + (int64_t)UV * VT);
 #pragma unroll
-        for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x; t < t_end; t += VT) {
+        for (int64_t t = t0 + threadIdx.x; t < t_end; t += VT) {
             const T di = A.dinv[t];
             // x is touched only here: streamed with non-temporal hints so that the
             // last-level cache keeps the vectors the next matvec and gs reuse.
@@ -363,19 +387,26 @@ __global__ __launch_bounds__(VT) void k_cg_update(CgUpdateArgs<T> A)
             }
         }
     }
-    sh[0][threadIdx.x] = rz;
-    sh[1][threadIdx.x] = rr;
-    __syncthreads();
-    for (int s = VT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
-            sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
-        }
-        __syncthreads();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        rz += __shfl_xor(rz, off, 64);
+        rr += __shfl_xor(rr, off, 64);
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[0][wave] = rz;
+        sh[1][wave] = rr;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        A.partial[((int64_t)0 * A.nfields + f) * gridDim.x + blockIdx.x] = sh[0][0];
-        A.partial[((int64_t)1 * A.nfields + f) * gridDim.x + blockIdx.x] = sh[1][0];
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int q = 0; q < VT / 64; ++q) {
+            a += sh[0][q];
+            b += sh[1][q];
+        }
+        A.partial[((int64_t)0 * A.nfields + f) * gridDim.x + blockIdx.x] = a;
+        A.partial[((int64_t)1 * A.nfields + f) * gridDim.x + blockIdx.x] = b;
     }
 }
 
@@ -693,6 +724,13 @@ static unsigned gs_grid(int64_t work)
 extern "C" {
 
 unsigned sem_vec_grid(int64_t n) { return stream_grid(n); }
+// workgroups of the CG update in precision f32 ? FP32 : FP64
+unsigned sem_update_grid(int64_t n, int f32)
+{
+    const int64_t c = (int64_t)VT * (f32 ? UpdChunk<float>::UV : UpdChunk<double>::UV);
+    const int64_t g = (n + c - 1) / c;
+    return (unsigned)(g < 1 ? 1 : g);
+}
 
 }  // extern "C"
 
@@ -774,11 +812,13 @@ hipError_t sem_launch_cg_start(const CgFinishArgs *A, hipStream_t st)
 }
 hipError_t sem_launch_cg_update_f64(const CgUpdateArgs<double> *A, unsigned grid, hipStream_t st)
 {
+    if ((int64_t)grid * VT * UpdChunk<double>::UV < A->n) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_cg_update<double>, dim3(grid, A->nfields), dim3(VT), 0, st, *A);
     return hipGetLastError();
 }
 hipError_t sem_launch_cg_update_f32(const CgUpdateArgs<float> *A, unsigned grid, hipStream_t st)
 {
+    if ((int64_t)grid * VT * UpdChunk<float>::UV < A->n) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_cg_update<float>, dim3(grid, A->nfields), dim3(VT), 0, st, *A);
     return hipGetLastError();
 }
