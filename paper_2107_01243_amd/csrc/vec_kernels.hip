@@ -38,6 +38,10 @@ constexpr int RT = 1024;  // lanes of the single-workgroup reduction kernels
 #ifndef SEM_UPD64
 #define SEM_UPD64 2
 #endif
+#ifndef SEM_GS_EPL
+#define SEM_GS_EPL 2
+#endif
+constexpr int GEPL = SEM_GS_EPL;  // 64-entry segments per wave of the entry-parallel gs
 #ifndef SEM_UPD32
 #define SEM_UPD32 4
 #endif
@@ -129,8 +133,8 @@ __global__ __launch_bounds__(VT) void k_gs(GsArgs<T> A)
     }
 }
 
-// Entry-parallel gather-scatter: lane t owns shared entry t (ascending global id,
-// groups never straddle a wave).  Every lane of a group reads the group's values
+// Entry-parallel gather-scatter: a lane owns one shared entry in each of the
+// wave's segments of 64 (ascending global id, groups never straddle a segment).  Every lane of a group reads the group's values
 // from its neighbour lanes and sums them in ascending local order from +0, so all
 // copies receive the identical, canonical sum; then each lane writes its own copy.
 // The shuffle loop runs max_group times for the whole wave (all lanes active).
@@ -149,24 +153,41 @@ __global__ __launch_bounds__(VT) void k_gs_entries(GsArgs<T> A)
         for (int f = 0; f < A.nfields; ++f) live = live || !A.skip[f].stop;
         if (!live) return;
     }
-    const int64_t t = (int64_t)lb * VT + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const bool in = t < A.nent;
-    const int32_t e = in ? A.ent_idx[t] : -1;
-    const unsigned meta = in ? A.ent_meta[t] : 0u;
-    const int pos = (int)(meta & 0xffu), cnt = (int)(meta >> 8);
-    const int lead = lane - pos;
+    // each wave owns GEPL consecutive 64-entry segments; lane l handles entry l of
+    // each, so its GEPL index -> value loads are independent and in flight together
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t base = ((int64_t)lb * VT + (int64_t)wave * 64) * GEPL + lane;
+    int32_t e[GEPL];
+    int cnt[GEPL], lead[GEPL];
+#pragma unroll
+    for (int k = 0; k < GEPL; ++k) {
+        const int64_t t = base + 64 * k;
+        const bool in = t < A.nent;
+        e[k] = in ? A.ent_idx[t] : -1;
+        const unsigned meta = in ? A.ent_meta[t] : 0u;
+        cnt[k] = (int)(meta >> 8);
+        lead[k] = lane - (int)(meta & 0xffu);
+    }
     for (int f = 0; f < A.nfields; ++f) {
         if (A.skip && A.skip[f].stop) continue;
         T *u = A.u + f * A.n;
-        const T v = (e >= 0) ? u[e] : T(0);
-        T s = T(0);
-        for (int q = 0; q < A.max_group; ++q) {
-            const int src = lead + q;
-            const T x = __shfl(v, src < 64 ? src : lane, 64);
-            if (q < cnt) s += x;
+        T v[GEPL], s[GEPL];
+#pragma unroll
+        for (int k = 0; k < GEPL; ++k) {
+            v[k] = (e[k] >= 0) ? u[e[k]] : T(0);
+            s[k] = T(0);
         }
-        if (e >= 0) u[e] = s;
+        for (int q = 0; q < A.max_group; ++q) {
+#pragma unroll
+            for (int k = 0; k < GEPL; ++k) {
+                const int src = lead[k] + q;
+                const T x = __shfl(v[k], src < 64 ? src : lane, 64);
+                if (q < cnt[k]) s[k] += x;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < GEPL; ++k)
+            if (e[k] >= 0) u[e[k]] = s[k];
     }
     if (A.alpha_job && blockIdx.x == 0) {
         __shared__ double sh[VT];
@@ -740,7 +761,7 @@ template <typename T>
 static hipError_t launch_gs_t(const GsArgs<T> *A, hipStream_t st)
 {
     if (A->nent > 0) {
-        hipLaunchKernelGGL(k_gs_entries<T>, dim3(gs_grid(A->nent)), dim3(VT), 0, st, *A);
+        hipLaunchKernelGGL(k_gs_entries<T>, dim3(gs_grid((A->nent + GEPL - 1) / GEPL)), dim3(VT), 0, st, *A);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || A->npairs + A->nblocks == 0) return e;
         GsArgs<T> B = *A;
