@@ -162,8 +162,9 @@ def main():
         sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-30, max_iter=20, check_every=20,
                       raise_on_fail=False)
         x.zero_()
+        # poll after every FP32 iteration so that no launch is queued past a segment end
         sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-10, mixed="reliable", max_iter=20,
-                      check_every=20, raise_on_fail=False)
+                      check_every=1, raise_on_fail=False)
         # projection-space kernels: fill eight vectors, then one projection with l = 8
         proj = P.projection(20)
         for k in range(9):
