@@ -7,7 +7,8 @@ operand u ~ U[-1,1] (seed 0), load vector U[-1,1] (seed 1) assembled and masked.
 One step = the whole hot path once:
   (a) R back-to-back ax_helm launches (the paper's matrix-vector benchmark loop,
       Listing 2) on u, followed by ten gs_op launches,
-  (b) an FP64 Jacobi-PCG solve to relative residual 1e-10,
+  (b) FP64 Jacobi-PCG solves to relative residual 1e-10, in the two-reduction and the
+      single-reduction (Chronopoulos-Gear) forms,
   (c) the mixed solves to 1e-10: FP32 Jacobi-PCG with FP64 reliable updates, and
       FP64 flexible CG around an FP32 Jacobi-PCG.
 value = FP64 ax_helm GDOF/s = n_p / (average ax_helm launch time), from HIP events
@@ -106,7 +107,7 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one plain device copy of 2^27 doubles (reference "
                          "for counter scaling), --reps ax_helm launches, one gs_op, 20 PCG iterations "
-                         "and nine projection-space updates")
+                         "in each form and nine projection-space updates")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the multi-GPU path "
@@ -162,6 +163,9 @@ def main():
         sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-30, max_iter=20, check_every=20,
                       raise_on_fail=False)
         x.zero_()
+        x.zero_()
+        sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-30, max_iter=20, check_every=20,
+                      single_reduction=True, raise_on_fail=False)
         # poll after every FP32 iteration so that no launch is queued past a segment end
         sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-10, mixed="reliable", max_iter=20,
                       check_every=1, raise_on_fail=False)
@@ -189,6 +193,12 @@ def main():
         info64 = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, check_every=50)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        x.zero_()
+        info1 = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, check_every=50,
+                              single_reduction=True)
+        torch.cuda.synchronize()
+        t1r = time.perf_counter() - t1
         infom, tm, infof, tf = None, None, None, None
         if not a.no_mixed:
             t1 = time.perf_counter()
@@ -211,6 +221,9 @@ def main():
             record["pcg64_s"].append(t64)
             record["it64"].append(info64[0]["iters"])
             record["tr64"].append(info64[0]["true_rel_res"])
+            record["cg1_s"].append(t1r)
+            record["cg1_it"].append(info1[0]["iters"])
+            record["cg1_tr"].append(info1[0]["true_rel_res"])
             if infom is not None:
                 record["mixed_s"].append(tm)
                 record["outer"].append(infom[0]["iters"])
@@ -243,13 +256,14 @@ def main():
         step(None)
         log(f"warmup {i + 1}/{a.warmup} done")
     rec = {k: [] for k in ("ax_ms", "gs_ms", "pcg64_s", "it64", "tr64", "mixed_s", "outer", "inner", "trm",
-                           "fcg_s", "fcg_outer", "fcg_inner", "fcg_tr")}
+                           "fcg_s", "fcg_outer", "fcg_inner", "fcg_tr", "cg1_s", "cg1_it", "cg1_tr")}
     torch.cuda.synchronize()
     tb = time.perf_counter()
     for i in range(a.steps):
         step(rec)
         log(f"step {i + 1}/{a.steps}: ax {rec['ax_ms'][-1] / a.reps * 1e3:.1f} us/launch, "
-            f"pcg64 {rec['pcg64_s'][-1]:.3f}s ({rec['it64'][-1]} it)"
+            f"pcg64 {rec['pcg64_s'][-1]:.3f}s ({rec['it64'][-1]} it), "
+            f"single-reduction {rec['cg1_s'][-1]:.3f}s ({rec['cg1_it'][-1]} it)"
             + (f", mixed {rec['mixed_s'][-1]:.3f}s ({rec['outer'][-1]} replacements / {rec['inner'][-1]} it)"
                f", fcg {rec['fcg_s'][-1]:.3f}s ({rec['fcg_outer'][-1]} outer / {rec['fcg_inner'][-1]} inner)"
                if rec["mixed_s"] else ""))
@@ -306,6 +320,9 @@ def main():
         "pcg_fp64_iters": int(np.median(rec["it64"])),
         "pcg_fp64_true_rel_res": float(np.max(rec["tr64"])),
         "pcg_fp64_ms_per_iter": round(float(np.median(rec["pcg64_s"])) / max(1, int(np.median(rec["it64"]))) * 1e3, 4),
+        "pcg_fp64_single_reduction_solve_s": round(float(np.median(rec["cg1_s"])), 4),
+        "pcg_fp64_single_reduction_iters": int(np.median(rec["cg1_it"])),
+        "pcg_fp64_single_reduction_true_rel_res": float(np.max(rec["cg1_tr"])),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",

@@ -195,6 +195,11 @@ typedef struct {
                            A segment shorter than 8 iterations squares it for the
                            next one (floor 1e-3), so fast-converging systems are not
                            replaced every iteration.                                */
+    int variant;        /* mixed == 0 only.  0: two-reduction Jacobi-PCG (Hestenes-
+                           Stiefel form); 1: single-reduction form (Chronopoulos-Gear):
+                           both inner products of an iteration come from one pass, the
+                           one reduction phase per iteration that Section 10 asks for
+                           across GPUs; same iterates in exact arithmetic.          */
 } sem_pcg_params;
 
 typedef struct {

@@ -350,14 +350,15 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo<LX, T>
 }
 
 // ------------------------------------------------------------------ fused CG matvec
-// For each field f (skipped once its solve has stopped):
-//   p = dinv * r + beta_f * p     (beta_f = 0 on the first iteration)
-//   w = A_L p,   partial_f += sum p * w   (the unassembled identity p^T A p = p_L^T A_L p_L)
-// Partials are per workgroup; a separate kernel reduces them in a fixed order.
-template <int LX, typename T, int NF, bool GEN>
+// Two-reduction CG (CG1 = false): p = dinv r + beta p (stored), w = A_L p.
+// Single-reduction CG (CG1 = true, Chronopoulos-Gear): u = dinv r (not stored),
+// w = A_L u.  Either way the workgroup's partial sum of v . w (v = p or u) is written:
+// v^T A v by the unassembled identity of Eq. 10.
+template <int LX, typename T, int NF, bool GEN, bool CG1>
 __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
+    static_assert(S::NT >= 64, "the partial-sum reduction needs a full first wave");
     __shared__ Lds<LX, T> lds;
     __shared__ double red[NF][S::NT];
     const int tid = threadIdx.x;
@@ -389,13 +390,18 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DE
         part[f] = 0.0;
         const CgScalars *sc = A.scal + f;
         if (sc->stop) continue;  // uniform: every lane reads the same flag
-        const T beta = (T)sc->beta;
         T r[LX], p[LX];
         load_row<LX, T>(r, A.r + f * A.n + row, act);
-        load_row<LX, T>(p, A.p + f * A.n + row, act);
+        if constexpr (CG1) {
 #pragma unroll
-        for (int i = 0; i < LX; ++i) p[i] = fma(beta, p[i], dinv[i] * r[i]);
-        store_row<LX, T>(A.p + f * A.n + row, p, act);
+            for (int i = 0; i < LX; ++i) p[i] = dinv[i] * r[i];
+        } else {
+            const T beta = (T)sc->beta;
+            load_row<LX, T>(p, A.p + f * A.n + row, act);
+#pragma unroll
+            for (int i = 0; i < LX; ++i) p[i] = fma(beta, p[i], dinv[i] * r[i]);
+            store_row<LX, T>(A.p + f * A.n + row, p, act);
+        }
         T ur[LX], us[LX], ut[LX];
         grad<LX, T>(D, p, s0, s1, a, b, ur, us, ut);
         apply_G<LX, T, GEN>(g, c, A.h1s, ur, us, ut);
@@ -411,16 +417,16 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DE
     // workgroup reduction in a fixed order (deterministic): the first wave (always
     // full, NT >= 64) sums strided slices, then a butterfly inside that wave.
 #pragma unroll
-    for (int f = 0; f < NF; ++f) red[f][tid] = part[f];
+    for (int q = 0; q < NF; ++q) red[q][tid] = part[q];
     __syncthreads();
     if (tid < 64) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
+        for (int q = 0; q < NF; ++q) {
             double v = 0.0;
-            for (int q = tid; q < S::NT; q += 64) v += red[f][q];
+            for (int k = tid; k < S::NT; k += 64) v += red[q][k];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (tid == 0) A.partial[(int64_t)f * gridDim.x + blockIdx.x] = v;
+            if (tid == 0) A.partial[(int64_t)q * gridDim.x + blockIdx.x] = v;
         }
     }
 }
@@ -603,7 +609,7 @@ hipError_t launch_ax(const sem::AxArgs<T> &A, const double *D, int nfields, hipS
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool CG1>
 hipError_t launch_cg(const sem::CgMatvecArgs<T> &A, const double *D, int nfields, hipStream_t st)
 {
     using S = sem::Shape<SEM_LX, T>;
@@ -612,11 +618,11 @@ hipError_t launch_cg(const sem::CgMatvecArgs<T> &A, const double *D, int nfields
     const auto Dm = make_deo<SEM_LX, T>(D);
     const bool gen = A.h1 || A.h2 || A.h2s != T(0);
     if (nfields == 3) {
-        if (gen) hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3, true>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
-        else hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3, false>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+        if (gen) hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3, true, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+        else hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3, false, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
     } else {
-        if (gen) hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1, true>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
-        else hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1, false>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+        if (gen) hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1, true, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+        else hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1, false, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
     }
     return hipGetLastError();
 }
@@ -648,12 +654,17 @@ hipError_t SEM_PASTE(sem_launch_ax_f32_lx, SEM_LX)(const sem::AxArgs<float> *A, 
 hipError_t SEM_PASTE(sem_launch_cg_f64_lx, SEM_LX)(const sem::CgMatvecArgs<double> *A,
                                                     const double *D, int nfields, hipStream_t st)
 {
-    return launch_cg<double>(*A, D, nfields, st);
+    return launch_cg<double, false>(*A, D, nfields, st);
 }
 hipError_t SEM_PASTE(sem_launch_cg_f32_lx, SEM_LX)(const sem::CgMatvecArgs<float> *A,
                                                     const double *D, int nfields, hipStream_t st)
 {
-    return launch_cg<float>(*A, D, nfields, st);
+    return launch_cg<float, false>(*A, D, nfields, st);
+}
+hipError_t SEM_PASTE(sem_launch_cg1_f64_lx, SEM_LX)(const sem::CgMatvecArgs<double> *A,
+                                                     const double *D, int nfields, hipStream_t st)
+{
+    return launch_cg<double, true>(*A, D, nfields, st);
 }
 hipError_t SEM_PASTE(sem_launch_adj_f64_lx, SEM_LX)(const sem::AdjArgs<double> *A, const double *D,
                                                      hipStream_t st)

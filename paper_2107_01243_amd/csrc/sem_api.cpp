@@ -41,6 +41,8 @@ using namespace sem;
                                                   hipStream_t);                                             \
     extern "C" hipError_t sem_launch_cg_f32_lx##L(const CgMatvecArgs<float> *, const double *, int,         \
                                                   hipStream_t);                                             \
+    extern "C" hipError_t sem_launch_cg1_f64_lx##L(const CgMatvecArgs<double> *, const double *, int,       \
+                                                   hipStream_t);                                            \
     extern "C" hipError_t sem_launch_adj_f64_lx##L(const AdjArgs<double> *, const double *, hipStream_t);   \
     extern "C" hipError_t sem_launch_adj_f32_lx##L(const AdjArgs<float> *, const double *, hipStream_t);    \
     extern "C" hipError_t sem_launch_geom_lx##L(const GeomArgs *, const double *, const double *,           \
@@ -67,6 +69,7 @@ hipError_t sem_launch_cg_start(const CgFinishArgs *, hipStream_t);
 hipError_t sem_launch_cg_update_f64(const CgUpdateArgs<double> *, unsigned, hipStream_t);
 hipError_t sem_launch_cg_update_f32(const CgUpdateArgs<float> *, unsigned, hipStream_t);
 hipError_t sem_launch_cg_finish(const CgFinishArgs *, hipStream_t);
+hipError_t sem_launch_cg1_update(const Cg1UpdateArgs *, hipStream_t);
 hipError_t sem_launch_dots(const DotArgs *, unsigned, hipStream_t);
 hipError_t sem_launch_rel_restart(const RelRestartArgs *, unsigned, hipStream_t);
 hipError_t sem_launch_cg_replace_f64(const double *, const double *, const uint8_t *, const int *, double *, int64_t,
@@ -95,6 +98,7 @@ struct LxFns {
     hipError_t (*ax32)(const AxArgs<float> *, const double *, int, hipStream_t);
     hipError_t (*cg64)(const CgMatvecArgs<double> *, const double *, int, hipStream_t);
     hipError_t (*cg32)(const CgMatvecArgs<float> *, const double *, int, hipStream_t);
+    hipError_t (*cg1)(const CgMatvecArgs<double> *, const double *, int, hipStream_t);
     hipError_t (*adj64)(const AdjArgs<double> *, const double *, hipStream_t);
     hipError_t (*adj32)(const AdjArgs<float> *, const double *, hipStream_t);
     hipError_t (*geom)(const GeomArgs *, const double *, const double *, hipStream_t);
@@ -107,6 +111,7 @@ const LxFns &fns(int lx)
 {
 #define SEM_ROW(L)                                                                                 \
     {sem_launch_ax_f64_lx##L, sem_launch_ax_f32_lx##L, sem_launch_cg_f64_lx##L, sem_launch_cg_f32_lx##L, \
+     sem_launch_cg1_f64_lx##L,                                                                     \
      sem_launch_adj_f64_lx##L, sem_launch_adj_f32_lx##L, sem_launch_geom_lx##L, sem_launch_diag_lx##L,  \
      sem_cg_nblocks_f64_lx##L, sem_cg_nblocks_f32_lx##L},
     static const LxFns table[] = {SEM_LX_LIST(SEM_ROW)};
@@ -227,10 +232,13 @@ struct Work {
     float *ri32 = nullptr;
     double *partial = nullptr;
     int64_t partial_len = 0;
+    int64_t nb = 0;                 // partial sums per row of W.partial
     CgScalars *scal = nullptr;      // device [fields]
     CgScalars *h_scal = nullptr;    // pinned mirror
     AlphaJob *job64 = nullptr;      // device, for the FP64 matvec grid
     AlphaJob *job32 = nullptr;      // device, for the FP32 matvec grid
+    AlphaJob *job_cg1 = nullptr;    // device, single-reduction CG fold (FP64 matvec grid)
+    double *s = nullptr;            // single-reduction CG: s = A p (FP64), allocated on first use
     double *dots = nullptr;         // device results of k_dots_finish
     double *h_dots = nullptr;       // pinned mirror
     double *fcg = nullptr;          // device: beta[3], alpha[3], norm[3], inv_norm[3]
@@ -244,6 +252,7 @@ struct Work {
         dfree(r); dfree(p); dfree(w); dfree(z); dfree(q);
         dfree(r32); dfree(y32); dfree(p32); dfree(w32); dfree(ri32);
         dfree(partial); dfree(scal); dfree(job64); dfree(job32); dfree(dots); dfree(fcg); dfree(done); dfree(rel);
+        dfree(job_cg1); dfree(s);
         if (h_rel) (void)hipHostFree(h_rel);
         h_rel = nullptr;
         if (h_scal) (void)hipHostFree(h_scal);
@@ -251,7 +260,7 @@ struct Work {
         if (h_fcg) (void)hipHostFree(h_fcg);
         if (h_done) (void)hipHostFree(h_done);
         h_scal = nullptr; h_dots = nullptr; h_fcg = nullptr; h_done = nullptr;
-        cap_n = 0; cap_f = 0; mixed = false; partial_len = 0;
+        cap_n = 0; cap_f = 0; mixed = false; partial_len = 0; nb = 0;
     }
 };
 
@@ -452,11 +461,14 @@ sem_status ensure_work(sem_coef c, int nf, bool mixed)
     const int64_t nb = std::max<int64_t>({fns(c->lx).nblk64(c->nelv), fns(c->lx).nblk32(c->nelv),
                                           (int64_t)sem_vec_grid(n), (int64_t)sem_update_grid(n, 0),
                                           (int64_t)sem_update_grid(n, 1)});
-    W.partial_len = 4 * (int64_t)nf * nb;
+    // 4 rows per field, plus the single-reduction update partials at offset 3 nb
+    W.partial_len = (4 * (int64_t)nf + 3) * nb;
+    W.nb = nb;
     SEM_TRY(dalloc(&W.partial, W.partial_len));
     SEM_TRY(dalloc(&W.scal, nf));
     SEM_TRY(dalloc(&W.job64, 1));
     SEM_TRY(dalloc(&W.job32, 1));
+    SEM_TRY(dalloc(&W.job_cg1, 1));
     SEM_TRY(dalloc(&W.dots, 4 * nf));
     SEM_TRY(dalloc(&W.fcg, 4 * nf));
     SEM_TRY(dalloc(&W.done, nf));
@@ -470,6 +482,11 @@ sem_status ensure_work(sem_coef c, int nf, bool mixed)
     const AlphaJob j32{W.partial, fns(c->lx).nblk32(c->nelv), W.scal};
     HIP_TRY(hipMemcpy(W.job64, &j64, sizeof(AlphaJob), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(W.job32, &j32, sizeof(AlphaJob), hipMemcpyHostToDevice));
+    // single-reduction fold: matvec partials [f][nblk64] at the start of W.partial, the
+    // update's [2][f][grid] after three rows of nb (clear of the matvec's up to 3 fields)
+    const AlphaJob j1{W.partial, fns(c->lx).nblk64(c->nelv), W.scal, 1, W.partial + 3 * nb,
+                      (int64_t)sem_vec_grid(n)};
+    HIP_TRY(hipMemcpy(W.job_cg1, &j1, sizeof(AlphaJob), hipMemcpyHostToDevice));
     W.cap_n = n;
     W.cap_f = nf;
     W.mixed = mixed;
@@ -1017,6 +1034,128 @@ sem_status sem_stream_triad(double *a, const double *b, const double *c, double 
 }
 
 // ------------------------------------------------------------------ solver
+// Single-reduction Jacobi-PCG (Chronopoulos-Gear) in FP64.  Per iteration: update
+// (p, s, x, r), matvec of r (u = dinv r, w = A_L u, partials of (r,u), (u,Au), (r,r)),
+// gather-scatter of w whose first workgroup folds the scalars.  After the recursive
+// residual meets rtol the true residual is checked; a field that misses it restarts
+// the recurrences from its current iterate (beta = 0), keeping its iteration count.
+static sem_status pcg_cg1(double *x, const double *b, int nf, sem_coef c, sem_gs g, const sem_pcg_params *P,
+                          sem_pcg_info *info, hipStream_t st)
+{
+    Work &W = c->ws;
+    const int64_t n = c->n, nn = n * nf;
+    if (!W.s) SEM_TRY(dalloc(&W.s, (size_t)W.cap_n * W.cap_f));
+    // initial residual and scalars exactly as for the two-reduction form
+    if (P->use_x0) {
+        SEM_TRY(launch_ax<double>(c, W.w, x, nf, st));
+        SEM_TRY(launch_gs<double>(W.w, nf, g, nullptr, nullptr, st));
+    } else {
+        HIP_TRY(sem_launch_fill_f64(x, 0.0, nn, st));
+    }
+    for (int f = 0; f < nf; ++f) {
+        CgScalars s{};
+        s.rtol = P->rtol;
+        s.max_iter = P->max_iter;
+        W.h_scal[f] = s;
+    }
+    HIP_TRY(hipMemcpyAsync(W.scal, W.h_scal, sizeof(CgScalars) * nf, hipMemcpyHostToDevice, st));
+    const unsigned vg = sem_vec_grid(n);
+    {
+        CgInitArgs<double> A{b, P->use_x0 ? W.w : nullptr, W.r, W.p, c->dinv, g->d_owner, W.partial, n, nf};
+        HIP_TRY(sem_launch_cg_init_f64(&A, vg, st));
+        CgFinishArgs F{W.partial, (int64_t)vg, W.scal, nullptr, 0, nf};
+        HIP_TRY(sem_launch_cg_start(&F, st));
+    }
+    HIP_TRY(sem_launch_fill_f64(W.s, 0.0, nn, st));
+    CgMatvecArgs<double> M{};
+    M.r = W.r;
+    M.w = W.w;
+    M.dinv = c->dinv;
+    M.G = c->G; M.B = c->B; M.h1 = c->h1; M.h2 = c->h2; M.h1s = c->h1s; M.h2s = c->h2s;
+    M.n = n;
+    M.nelv = c->nelv;
+    M.scal = W.scal;
+    M.partial = W.partial;
+    // the update's partials go where the fold job reads them (see ensure_work)
+    const Cg1UpdateArgs U{x, W.r, W.p, W.s, W.w, c->dinv, g->d_owner, W.scal, W.partial + 3 * W.nb, n, nf};
+    auto prime = [&]() -> sem_status {  // matvec of the current r and the first fold
+        HIP_TRY(fns(c->lx).cg1(&M, c->Xh->D, nf, st));
+        return launch_gs<double>(W.w, nf, g, W.scal, W.job_cg1, st);
+    };
+    auto iterate = [&]() -> sem_status {
+        const int check_every = std::max(1, P->check_every);
+        const int64_t max_batches = (int64_t)(P->max_iter + check_every - 1) / check_every + 2;
+        HIP_TRY(hipMemcpyAsync(W.h_scal, W.scal, sizeof(CgScalars) * nf, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int64_t bt = 0; bt < max_batches; ++bt) {
+            bool all = true;
+            int done_max = 0;
+            for (int f = 0; f < nf; ++f) {
+                all = all && W.h_scal[f].stop;
+                done_max = std::max(done_max, W.h_scal[f].iter);
+            }
+            if (all) break;
+            const int todo = std::min(check_every, std::max(1, P->max_iter - done_max));
+            for (int it = 0; it < todo; ++it) {
+                HIP_TRY(sem_launch_cg1_update(&U, st));
+                SEM_TRY(prime());
+            }
+            HIP_TRY(hipMemcpyAsync(W.h_scal, W.scal, sizeof(CgScalars) * nf, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        return SEM_OK;
+    };
+    SEM_TRY(prime());
+    SEM_TRY(iterate());
+    double tr[3];
+    for (int round = 0;; ++round) {
+        SEM_TRY(true_residual(c, g, nf, x, b, tr, st));  // leaves b - A x in W.r
+        bool any = false;
+        for (int f = 0; f < nf; ++f) {
+            CgScalars &s = W.h_scal[f];
+            const bool redo = s.status == 0 && P->rtol > 0 && s.bb > 0 && tr[f] > P->rtol && s.iter < P->max_iter;
+            if (redo) {
+                s.stop = 0;
+                s.primed = 0;
+            } else {
+                s.stop = 1;
+            }
+            any = any || redo;
+        }
+        if (!any || round >= 16) break;
+        // restart the fields that missed rtol from their current iterate: r is the
+        // true residual (with its (r, dinv r) and (r, r)), p and s start from zero
+        // (beta = 0 at the first fold)
+        for (int f = 0; f < nf; ++f) W.h_done[f] = W.h_scal[f].stop ? 0 : 1;
+        HIP_TRY(hipMemcpyAsync(W.scal, W.h_scal, sizeof(CgScalars) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(W.done, W.h_done, sizeof(int) * nf, hipMemcpyHostToDevice, st));
+        HIP_TRY(sem_launch_cg_replace_f64(W.r, c->dinv, g->d_owner, W.done, W.partial, n, nf, st));
+        CgFinishArgs F{W.partial, (int64_t)vg, W.scal, nullptr, 0, nf};
+        HIP_TRY(sem_launch_cg_resume(&F, W.done, st));
+        HIP_TRY(sem_launch_fill_f64(W.p, 0.0, nn, st));
+        HIP_TRY(sem_launch_fill_f64(W.s, 0.0, nn, st));
+        SEM_TRY(prime());
+        SEM_TRY(iterate());
+    }
+    sem_status out = SEM_OK;
+    for (int f = 0; f < nf; ++f) {
+        const CgScalars &s = W.h_scal[f];
+        const double rel = s.bb == 0.0 ? 0.0 : std::sqrt(s.rr / s.bb);
+        const bool conv = s.status == 0 && std::isfinite(rel) && (P->rtol <= 0 || (rel <= P->rtol && tr[f] <= P->rtol));
+        if (info) {
+            info[f].iters = s.iter;
+            info[f].inner_iters = 0;
+            info[f].converged = conv ? 1 : 0;
+            info[f].rel_res = rel;
+            info[f].true_rel_res = tr[f];
+        }
+        if (s.status == 2) out = fail(SEM_ERR_BREAKDOWN, "CG breakdown in field %d at iteration %d", f, s.iter);
+        else if (!conv && out == SEM_OK)
+            out = fail(SEM_ERR_NOT_CONVERGED, "field %d: |r|/|b| = %.3e after %d iterations", f, rel, s.iter);
+    }
+    return out;
+}
+
 static sem_status pcg_fp64(double *x, const double *b, int nf, sem_coef c, sem_gs g, const sem_pcg_params *P,
                            sem_pcg_info *info, hipStream_t st)
 {
@@ -1325,6 +1464,8 @@ sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef,
         if (!(coef->flags & SEM_COEF_F32)) return fail(SEM_ERR_INVALID, "mixed solve needs a coef created with SEM_COEF_F32");
         if (P.rtol <= 0) return fail(SEM_ERR_INVALID, "mixed solve needs rtol > 0");
     }
+    if (P.variant != 0 && P.variant != 1) return fail(SEM_ERR_INVALID, "variant must be 0 or 1");
+    if (P.variant == 1 && P.mixed != 0) return fail(SEM_ERR_INVALID, "the single-reduction form is FP64 only (mixed = 0)");
     if (P.mixed == 1 && !(P.delta == 0.0 || (P.delta > 0.0 && P.delta < 1.0)))
         return fail(SEM_ERR_INVALID, "delta must be 0 (default) or in (0, 1)");
     if (P.mixed == 2) {
@@ -1341,6 +1482,7 @@ sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef,
     SEM_TRY(ensure_work(coef, nfields, P.mixed != 0));
     if (P.mixed == 1) return pcg_mixed_reliable(x, b, nfields, coef, gs, &P, info, st);
     if (P.mixed == 2) return pcg_mixed(x, b, nfields, coef, gs, &P, info, st);
+    if (P.variant == 1) return pcg_cg1(x, b, nfields, coef, gs, &P, info, st);
     return pcg_fp64(x, b, nfields, coef, gs, &P, info, st);
 }
 

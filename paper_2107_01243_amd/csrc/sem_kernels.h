@@ -64,9 +64,11 @@ struct CgScalars {
     int max_iter;
     int stop;       // nonzero: this field's iterates are frozen
     int status;     // 0 running/converged, 1 not converged, 2 breakdown
+    int primed;     // single-reduction CG: 0 until the first step length is set
 };
 
-// p = dinv r + beta p;  w = A_L p;  per-workgroup partial sums of p.w
+// p = dinv r + beta p;  w = A_L p;  per-workgroup partial sums of p.w.
+// Single-reduction form: u = dinv r;  w = A_L u;  partial sums of u.w.
 template <typename T>
 struct CgMatvecArgs {
     T *p;

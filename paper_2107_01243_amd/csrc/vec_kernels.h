@@ -8,11 +8,35 @@
 
 namespace sem {
 
-// Step length of CG folded into the gather-scatter launch: alpha_f = rz_f / pw_f.
+// CG scalars folded into the gather-scatter launch from the partial sums of the
+// kernels before it.  partial [field][nblk]: the matvec's (v, A v).
+// mode 0 (two-reduction CG): alpha_f = rz_f / (p, A p)_f.
+// mode 1 (single-reduction CG): with (r, u) and (r, r) from the update's partials
+// partial2 [2][field][nblk2] (or, before the first step, from the scalars), gives
+// beta, alpha, the iteration count and the stopping state.
 struct AlphaJob {
-    const double *partial;  // [field][nblk] partial sums of p.A_L p
+    const double *partial;
     int64_t nblk;
     CgScalars *scal;
+    int mode;
+    const double *partial2;
+    int64_t nblk2;
+};
+
+// Single-reduction CG update: p = dinv r + beta p; s = w + beta s; x += alpha p;
+// r -= alpha s (not on Dirichlet points); partial sums of the new (r, dinv r), (r, r).
+struct Cg1UpdateArgs {
+    double *x;
+    double *r;
+    double *p;
+    double *s;
+    const double *w;
+    const double *dinv;
+    const uint8_t *owner;
+    const CgScalars *scal;
+    double *partial;  // [2][field][grid]: (r, dinv r), (r, r) of the updated r
+    int64_t n;
+    int nfields;
 };
 
 template <typename T>

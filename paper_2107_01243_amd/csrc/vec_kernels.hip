@@ -80,6 +80,81 @@ __device__ double block_sum_fixed(const double *part, int64_t nblk, double *sh)
     return r;
 }
 
+// Single-reduction CG (Chronopoulos-Gear) scalars once r_k and w_k = A u_k are known
+// (u_k = dinv r_k): gamma = (r_k, u_k), delta = (u_k, A u_k), rr = (r_k, r_k).  On the
+// first call (primed == 0) beta = 0 and alpha = gamma / delta; afterwards
+// beta = gamma / gamma_old and alpha = gamma / (delta - beta gamma / alpha_old), which
+// reproduce the two-reduction CG recurrences in exact arithmetic.
+__device__ inline void cg1_fold(CgScalars &s, double gamma, double delta, double rr)
+{
+    if (s.stop) return;
+    const bool first = s.primed == 0;
+    if (!first) s.iter += 1;
+    s.rr = rr;
+    const double rel = s.bb > 0.0 ? sqrt(rr / s.bb) : 0.0;
+    if (!isfinite(gamma) || !isfinite(delta) || !isfinite(rr)) {
+        s.stop = 1;
+        s.status = 2;
+        return;
+    }
+    if ((s.rtol > 0.0 && rel <= s.rtol) || gamma == 0.0) {
+        s.stop = 1;
+        s.rz = gamma;
+        return;
+    }
+    if (s.iter >= s.max_iter) {
+        s.stop = 1;
+        s.status = (s.rtol > 0.0) ? 1 : 0;
+        return;
+    }
+    const double beta = first ? 0.0 : gamma / s.rz;
+    const double den = first ? delta : delta - beta * gamma / s.alpha;
+    if (!(den > 0.0) || !isfinite(den)) {
+        s.stop = 1;
+        s.status = 2;
+        s.alpha = 0.0;
+        return;
+    }
+    s.beta = beta;
+    s.alpha = gamma / den;
+    s.rz = gamma;
+    s.primed = 1;
+}
+
+// Fold of the CG scalars for every field by workgroup 0 of a gather-scatter launch
+// (the matvec whose partials it reads ended before this launch began).
+template <int NTH>
+__device__ void fold_job(const AlphaJob &J, int nfields, double *sh)
+{
+    for (int f = 0; f < nfields; ++f) {
+        if (J.mode == 0) {
+            const double pw = block_sum_fixed<NTH>(J.partial + f * J.nblk, J.nblk, sh);
+            if (threadIdx.x == 0) {
+                CgScalars &sc = J.scal[f];
+                if (!sc.stop) {
+                    if (!(pw > 0.0) || !isfinite(pw) || !isfinite(sc.rz)) {
+                        sc.stop = 1;
+                        sc.status = 2;
+                        sc.alpha = 0.0;
+                    } else {
+                        sc.alpha = sc.rz / pw;
+                    }
+                }
+            }
+        } else {
+            const double d = block_sum_fixed<NTH>(J.partial + f * J.nblk, J.nblk, sh);
+            CgScalars &sc = J.scal[f];
+            double g = sc.rz, rr = sc.rr;  // before the first step: from the start kernels
+            if (sc.primed) {               // uniform: every lane reads the same flag
+                g = block_sum_fixed<NTH>(J.partial2 + (0 * nfields + f) * J.nblk2, J.nblk2, sh);
+                rr = block_sum_fixed<NTH>(J.partial2 + (1 * nfields + f) * J.nblk2, J.nblk2, sh);
+            }
+            if (threadIdx.x == 0) cg1_fold(sc, g, d, rr);
+            __syncthreads();  // the next field's reads follow lane 0's update
+        }
+    }
+}
+
 // ------------------------------------------------------------------ gather-scatter
 template <typename T>
 __global__ __launch_bounds__(VT) void k_gs(GsArgs<T> A)
@@ -114,22 +189,7 @@ __global__ __launch_bounds__(VT) void k_gs(GsArgs<T> A)
     // matvec's partials (complete, since that kernel ended before this one began).
     if (A.alpha_job && blockIdx.x == 0) {
         __shared__ double sh[VT];
-        const AlphaJob &J = *A.alpha_job;
-        for (int f = 0; f < A.nfields; ++f) {
-            const double pw = block_sum_fixed<VT>(J.partial + f * J.nblk, J.nblk, sh);
-            if (threadIdx.x == 0) {
-                CgScalars &s = J.scal[f];
-                if (!s.stop) {
-                    if (!(pw > 0.0) || !isfinite(pw) || !isfinite(s.rz)) {
-                        s.stop = 1;
-                        s.status = 2;
-                        s.alpha = 0.0;
-                    } else {
-                        s.alpha = s.rz / pw;
-                    }
-                }
-            }
-        }
+        fold_job<VT>(*A.alpha_job, A.nfields, sh);
     }
 }
 
@@ -191,22 +251,7 @@ __global__ __launch_bounds__(VT) void k_gs_entries(GsArgs<T> A)
     }
     if (A.alpha_job && blockIdx.x == 0) {
         __shared__ double sh[VT];
-        const AlphaJob &J = *A.alpha_job;
-        for (int f = 0; f < A.nfields; ++f) {
-            const double pw = block_sum_fixed<VT>(J.partial + f * J.nblk, J.nblk, sh);
-            if (threadIdx.x == 0) {
-                CgScalars &sc = J.scal[f];
-                if (!sc.stop) {
-                    if (!(pw > 0.0) || !isfinite(pw) || !isfinite(sc.rz)) {
-                        sc.stop = 1;
-                        sc.status = 2;
-                        sc.alpha = 0.0;
-                    } else {
-                        sc.alpha = sc.rz / pw;
-                    }
-                }
-            }
-        }
+        fold_job<VT>(*A.alpha_job, A.nfields, sh);
     }
 }
 
@@ -405,6 +450,67 @@ __global__ __launch_bounds__(VT) void k_cg_update(CgUpdateArgs<T> A)
             if (A.owner[t]) {
                 rz += (double)ri * (double)(di * ri);
                 rr += (double)ri * (double)ri;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        rz += __shfl_xor(rz, off, 64);
+        rr += __shfl_xor(rr, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[0][wave] = rz;
+        sh[1][wave] = rr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int q = 0; q < VT / 64; ++q) {
+            a += sh[0][q];
+            b += sh[1][q];
+        }
+        A.partial[((int64_t)0 * A.nfields + f) * gridDim.x + blockIdx.x] = a;
+        A.partial[((int64_t)1 * A.nfields + f) * gridDim.x + blockIdx.x] = b;
+    }
+}
+
+// Single-reduction CG update (Chronopoulos-Gear): with u = dinv r recomputed on the
+// fly, p = u + beta p, s = w + beta s (s = A p carried as a vector), x += alpha p,
+// r -= alpha s on non-Dirichlet points, and the partial sums of the new (r, dinv r)
+// and (r, r) over owned points (wave butterflies, then the waves in order).  They are
+// reduced together with the next matvec's (u, A u): one reduction phase per iteration.
+__global__ __launch_bounds__(VT) void k_cg1_update(Cg1UpdateArgs A)
+{
+    __shared__ double sh[2][VT / 64];
+    const int f = blockIdx.y;
+    const CgScalars &sc = A.scal[f];
+    double rz = 0.0, rr = 0.0;
+    if (!sc.stop) {
+        const double alpha = sc.alpha, beta = sc.beta;
+        double *x = A.x + f * A.n;
+        double *r = A.r + f * A.n;
+        double *p = A.p + f * A.n;
+        double *s = A.s + f * A.n;
+        const double *w = A.w + f * A.n;
+        const int64_t t_end = min(A.n, (int64_t)(blockIdx.x + 1) * CHUNK);
+#pragma unroll
+        for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x; t < t_end; t += VT) {
+            const double di = A.dinv[t];
+            double ri = r[t];
+            const double pn = fma(beta, p[t], di * ri);
+            const double sn = fma(beta, s[t], w[t]);
+            p[t] = pn;
+            s[t] = sn;
+            __builtin_nontemporal_store(fma(alpha, pn, __builtin_nontemporal_load(x + t)), x + t);
+            if (di != 0.0) {
+                ri = fma(-alpha, sn, ri);
+                r[t] = ri;
+            }
+            if (A.owner[t]) {
+                rz += ri * (di * ri);
+                rr += ri * ri;
             }
         }
     }
@@ -841,6 +947,13 @@ hipError_t sem_launch_cg_update_f32(const CgUpdateArgs<float> *A, unsigned grid,
 {
     if ((int64_t)grid * VT * UpdChunk<float>::UV < A->n) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_cg_update<float>, dim3(grid, A->nfields), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_cg1_update(const Cg1UpdateArgs *A, hipStream_t st)
+{
+    if (A->n == 0) return hipSuccess;
+    if (!A->owner || !A->partial) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cg1_update, dim3(stream_grid(A->n), A->nfields), dim3(VT), 0, st, *A);
     return hipGetLastError();
 }
 hipError_t sem_launch_cg_finish(const CgFinishArgs *A, hipStream_t st)

@@ -33,7 +33,7 @@ class SemError(RuntimeError):
 class PcgParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("mixed", C.c_int), ("inner_rtol", C.c_double), ("inner_max_iter", C.c_int),
-                ("use_x0", C.c_int), ("delta", C.c_double)]
+                ("use_x0", C.c_int), ("delta", C.c_double), ("variant", C.c_int)]
 
 
 class PcgInfo(C.Structure):
@@ -316,16 +316,18 @@ MIXED_MODES = {False: 0, True: 1, 0: 0, 1: 1, 2: 2, "fp64": 0, "reliable": 1, "f
 def pcg_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, nfields: int = 1, rtol: float = 1e-10,
               max_iter: int = 100000, check_every: int = 25, mixed=False,
               inner_rtol: float = 1e-4, inner_max_iter: int = 2000, use_x0: bool = False,
-              delta: float = 0.5, stream=None, raise_on_fail: bool = True):
+              delta: float = 0.5, single_reduction: bool = False, stream=None,
+              raise_on_fail: bool = True):
     """Solve mask QQ^T A_L x = b (Section 4 Jacobi-PCG).  mixed: False / "fp64" (FP64
     PCG), True / "reliable" (FP32 PCG with FP64 reliable updates), "fcg" (FP64 flexible
-    CG around an FP32 Jacobi-PCG).  Returns one info dict per field."""
+    CG around an FP32 Jacobi-PCG).  single_reduction (FP64 only): Chronopoulos-Gear
+    form with one reduction phase per iteration.  Returns one info dict per field."""
     _dev(x, nfields * msh.n, "x")
     _dev(b, nfields * msh.n, "b")
     if x.dtype != torch.float64 or b.dtype != torch.float64:
         raise TypeError("x and b must be float64")
     P = PcgParams(float(rtol), int(max_iter), int(check_every), MIXED_MODES[mixed], float(inner_rtol),
-                  int(inner_max_iter), int(bool(use_x0)), float(delta))
+                  int(inner_max_iter), int(bool(use_x0)), float(delta), int(bool(single_reduction)))
     info = (PcgInfo * nfields)()
     st = _L.sem_pcg_solve(_ptr(x), _ptr(b), nfields, coef._h, msh._h, Xh._h, gs._h, C.byref(P), info,
                           _stream(stream))

@@ -151,21 +151,24 @@ def test_pcg_full_size_32cubed_lx8():
     bl = workloads.uniform(P.n, workloads.SEED_RHS)
     b = P.assemble(to_dev(bl))
     x64, i64 = P.solve(b, rtol=wl.rtol, check_every=50)
+    x1, i1 = P.solve(b, rtol=wl.rtol, check_every=50, single_reduction=True)
     xm, im = P.solve(b, rtol=wl.rtol, mixed="reliable")
     xf, iff = P.solve(b, rtol=wl.rtol, mixed="fcg", inner_rtol=1e-4, inner_max_iter=5000)
-    X64, XM, XF = host(x64), host(xm), host(xf)
-    del P, x64, xm, xf, b
+    X64, X1, XM, XF = host(x64), host(x1), host(xm), host(xf)
+    del P, x64, x1, xm, xf, b
     torch.cuda.empty_cache()
-    say(f"   fp64 {i64[0]['iters']} it, reliable {im[0]['iters']} replacements / {im[0]['inner_iters']} it, "
-        f"fcg {iff[0]['iters']} outer / {iff[0]['inner_iters']} inner")
+    say(f"   fp64 {i64[0]['iters']} it, single reduction {i1[0]['iters']} it, reliable {im[0]['iters']} "
+        f"replacements / {im[0]['inner_iters']} it, fcg {iff[0]['iters']} outer / {iff[0]['inner_iters']} inner")
+    assert abs(i1[0]["iters"] - i64[0]["iters"]) <= max(2, math.ceil(0.01 * i64[0]["iters"]))
     O = oracle.Problem(wl.nx, wl.lx, wl.eps)
     bo = O.assemble_rhs(bl)
-    for X, info in ((X64, i64[0]), (XM, im[0]), (XF, iff[0])):
+    for X, info in ((X64, i64[0]), (X1, i1[0]), (XM, im[0]), (XF, iff[0])):
         tr = O.true_rel_res(X, bo)
         assert tr <= 1.05e-10, tr
         assert abs(info["true_rel_res"] - tr) <= 1e-2 * tr + 1e-13
     # both solutions meet the same residual bound; their difference is bounded by
     # kappa * 2e-10 (kappa ~ 1e4-1e5 for Jacobi-preconditioned Poisson at this size)
+    assert rel_inf(X1, X64) <= 1e-5
     assert rel_inf(XM, X64) <= 1e-5
     assert rel_inf(XF, X64) <= 1e-5
     assert np.abs(X64[O.dirichlet == 1]).max() == 0.0
@@ -276,6 +279,54 @@ def test_pcg_three_fields_and_initial_guess():
     info2 = sem.pcg_solve(x2, b, P.coef, P.msh, P.Xh, P.gs, nfields=3, rtol=1e-9, use_x0=True)
     assert all(d["iters"] == 0 for d in info2)
     P.coef.set_helmholtz(1.0, 0.0)
+
+
+# ------------------------------------------------------------------ single-reduction CG (next row f2)
+def test_single_reduction_fixed_iterations():
+    """Chronopoulos-Gear CG rearranges the two-reduction recurrences without changing
+    them in exact arithmetic: after 40 steps its iterate equals the oracle's textbook
+    PCG iterate (and the two-reduction GPU iterate) to rounding."""
+    say("[pcg single reduction, 40 steps]")
+    P, O = pair(4, 6)
+    P.coef.set_helmholtz(1.0, 0.0)
+    O.set_coef(1.0, 0.0)
+    bl = workloads.uniform(P.n, workloads.SEED_RHS)
+    bo = O.assemble_rhs(bl)
+    b = P.assemble(to_dev(bl))
+    xo, io = O.pcg(bo, rtol=0.0, max_iter=40)
+    x1, i1 = P.solve(b, rtol=0.0, max_iter=40, single_reduction=True, check_every=7)
+    x2, i2 = P.solve(b, rtol=0.0, max_iter=40, check_every=7)
+    assert i1[0]["iters"] == i2[0]["iters"] == io["iters"] == 40
+    say(f"   vs oracle {rel_inf(host(x1), xo):.2e}, vs two-reduction {rel_inf(host(x1), host(x2)):.2e}")
+    assert rel_inf(host(x1), xo) <= 1e-10
+    assert rel_inf(host(x1), host(x2)) <= 1e-10
+    assert abs(i1[0]["rel_res"] - io["rel_res"]) <= 1e-6 * io["rel_res"]
+
+
+@pytest.mark.parametrize("nx,lx,h2,nf", [(6, 8, 0.0, 1), (3, 12, 100.0, 1), (3, 8, 2000.0, 3)])
+def test_single_reduction_to_tolerance(nx, lx, h2, nf):
+    say(f"[pcg single reduction rtol] nx={nx} lx={lx} h2={h2} nf={nf}")
+    P, O = pair(nx, lx)
+    h1 = 1.0 if nf == 1 else 1.0 / 5000.0
+    P.coef.set_helmholtz(h1, h2)
+    O.set_coef(h1, h2)
+    seeds = workloads.SEED_RHS_FIELDS[:nf] if nf == 3 else (workloads.SEED_RHS,)
+    bls = [workloads.uniform(P.n, sd) for sd in seeds]
+    b = P.assemble(to_dev(np.concatenate(bls)), nfields=nf)
+    x, info = P.solve(b, nfields=nf, rtol=1e-10, check_every=20, single_reduction=True)
+    X = host(x).reshape(nf, -1)
+    for f in range(nf):
+        bo = O.assemble_rhs(bls[f])
+        xo, io = O.pcg(bo, rtol=1e-10)
+        it, ito = info[f]["iters"], io["iters"]
+        assert abs(it - ito) <= max(2, math.ceil(0.01 * ito)), (it, ito)
+        assert rel_inf(X[f], xo) <= 1e-8
+        tr = O.true_rel_res(X[f], bo)
+        assert tr <= 1.05e-10, tr
+        assert abs(info[f]["true_rel_res"] - tr) <= 1e-3 * tr + 1e-15
+    P.coef.set_helmholtz(1.0, 0.0)
+    with pytest.raises(sem.SemError, match="INVALID"):
+        P.solve(b, nfields=nf, rtol=1e-10, mixed="reliable", single_reduction=True)
 
 
 @pytest.mark.parametrize("mode", ["reliable", "fcg"])
