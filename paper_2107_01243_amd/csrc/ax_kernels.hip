@@ -35,14 +35,21 @@ namespace sem {
 
 // ------------------------------------------------------------------ launch shape
 // Elements per workgroup: fill whole wave64s where possible, keep the two LDS
-// transpose buffers within 64 KB (up to 160 KB for a single large element), and
-// aim at about 256 lanes per workgroup.
+// transpose buffers within 64 KB (up to 160 KB for a single large element), keep
+// the register budget that the workgroup's size leaves each lane above what a lane
+// needs, and aim at about 256 lanes per workgroup.
 template <int LX, typename T>
 struct Shape {
     static constexpr int NP = LX * LX;                       // lanes per element
     static constexpr int PAD = LX + 1;                       // LDS row stride
     static constexpr int ESZ = NP * PAD;                     // one LDS buffer, one element
     static constexpr int EBYTES = 2 * ESZ * (int)sizeof(T);  // LDS per element
+    // 32-bit registers a lane needs, estimated: six geometric-factor rows and about
+    // eight more pencil rows (u, its three derivatives, w, h1, h2 B, dinv), plus
+    // scalars.  A SIMD gives 512 per lane to one wave, 512 / k to each of k waves, and
+    // a workgroup of W waves puts ceil(W / 4) of them on one SIMD.
+    static constexpr int REGS = 14 * LX * (int)sizeof(T) / 4 + 40;
+    static constexpr int MAX_WAVES = 4 * (512 / REGS > 1 ? 512 / REGS : 1);
     static constexpr int pick()
     {
         int best = 1;
@@ -51,6 +58,7 @@ struct Shape {
             if (e > 1 && e * EBYTES > 64 * 1024) break;
             const int thr = e * NP;
             const int waves = (thr + 63) / 64;
+            if (e > 1 && waves > MAX_WAVES) break;
             const double waste = double(waves * 64 - thr) / double(waves * 64);
             const double dist = (thr > 256 ? thr - 256 : 256 - thr) / 1024.0;
             const double score = waste + 0.25 * dist;
