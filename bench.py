@@ -272,6 +272,43 @@ def main():
     cold_s = ax_cold()
     log(f"ax cold-cache {cold_s * 1e6:.1f} us/launch")
 
+    def t_launch(fn, reps=20):
+        """Average launch time (s) of fn over reps back-to-back launches, HIP events."""
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    # the other kernels of the path on the same mesh, each against its own bytes per
+    # point: FP32 ax_helm (8 words), the h1-adjoint (u, v, six G, g: 9 words), and the
+    # batched three-field Helmholtz operator (3 u, 3 w, six G, B: 13 words per point
+    # for three fields) with h1 = 1/Re, h2 = 1/dt of the velocity solves (Re = 5000,
+    # dt = 5e-4), in FP64 and FP32
+    kern = {}
+    u32, w32 = u.float(), torch.empty(P.n, dtype=torch.float32, device="cuda")
+    t = t_launch(lambda: sem.ax_helm(w32, u32, P.coef, P.msh, P.Xh))
+    kern["ax_f32"] = (t, 8 * 4)
+    g = torch.empty_like(u)
+    t = t_launch(lambda: sem.ax_helm_adjoint(g, u, w, P.coef, P.msh, P.Xh))
+    kern["adjoint_f64"] = (t, 9 * 8)
+    del g, u32, w32
+    P.coef.set_helmholtz(1.0 / 5000.0, 1.0 / 5e-4)
+    u3 = torch.from_numpy(np.concatenate([workloads.uniform(P.n, sd) for sd in (0, 5, 6)])).cuda()
+    w3 = torch.empty_like(u3)
+    t = t_launch(lambda: sem.ax_helm(w3, u3, P.coef, P.msh, P.Xh, 3))
+    kern["ax_batched3_f64"] = (t, 13 * 8)
+    u3, w3 = u3.float(), w3.float()
+    t = t_launch(lambda: sem.ax_helm(w3, u3, P.coef, P.msh, P.Xh, 3))
+    kern["ax_batched3_f32"] = (t, 13 * 4)
+    del u3, w3
+    P.coef.set_helmholtz(1.0, 0.0)
+    for k, (t, bpp) in kern.items():
+        log(f"{k}: {t * 1e6:.1f} us, {bpp * P.n / t / 1e9:.0f} GB/s")
+
     # projection onto previous solutions: a sequence of slowly varying loads (four
     # fixed patterns with drifting amplitudes, 1e-6 noise), FP64 solves to 1e-10 with a
     # space of 20 previous solutions; the first solve starts from an empty space
@@ -343,6 +380,10 @@ def main():
             "pcg_fcg_true_rel_res": float(np.max(rec["fcg_tr"])),
         })
     out["ax_unique_gdofs"] = round(wl.n_unique / ax_s / 1e9, 3)
+    out["other_kernels"] = {k: {"us": round(t * 1e6, 2), "bytes_per_point": bpp,
+                                "GBs": round(bpp * P.n / t / 1e9, 1),
+                                "frac": round(bpp * P.n / t / 1e9 / HBM_PEAK_GBS, 4)}
+                            for k, (t, bpp) in kern.items()}
     out["pcg_fp64_gpoint_iters_per_s"] = round(P.n * out["pcg_fp64_iters"] / out["pcg_fp64_solve_s"] / 1e9, 3)
     if proj_rec:
         warm = proj_rec[4:] if len(proj_rec) > 4 else proj_rec[-1:]
