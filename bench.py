@@ -107,7 +107,8 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one plain device copy of 2^27 doubles (reference "
                          "for counter scaling), --reps ax_helm launches, one gs_op, 20 PCG iterations "
-                         "in each form and nine projection-space updates")
+                         "in each form, five h1-adjoint and five batched three-field operator launches "
+                         "per precision, and nine projection-space updates")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the multi-GPU path "
@@ -169,6 +170,20 @@ def main():
         # poll after every FP32 iteration so that no launch is queued past a segment end
         sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-10, mixed="reliable", max_iter=20,
                       check_every=1, raise_on_fail=False)
+        # the h1-adjoint and the batched three-field Helmholtz operator (FP64, FP32)
+        g = torch.empty_like(u)
+        for _ in range(5):
+            sem.ax_helm_adjoint(g, u, w, P.coef, P.msh, P.Xh)
+        P.coef.set_helmholtz(1.0 / 5000.0, 1.0 / 5e-4)
+        u3 = torch.from_numpy(np.concatenate([workloads.uniform(P.n, sd) for sd in (0, 5, 6)])).cuda()
+        w3 = torch.empty_like(u3)
+        for _ in range(5):
+            sem.ax_helm(w3, u3, P.coef, P.msh, P.Xh, 3)
+        u3, w3 = u3.float(), w3.float()
+        for _ in range(5):
+            sem.ax_helm(w3, u3, P.coef, P.msh, P.Xh, 3)
+        del g, u3, w3
+        P.coef.set_helmholtz(1.0, 0.0)
         # projection-space kernels: fill eight vectors, then one projection with l = 8
         proj = P.projection(20)
         for k in range(9):
