@@ -6,9 +6,9 @@ It shares no code with the HIP path.  The arithmetic lives in
 ``sem_oracle.c`` (plain loops, FP64, ``-O2 -ffp-contract=off``); this module
 only marshals numpy arrays into it.
 
-The projection onto previous solutions (``Problem.projection``) is written
-here with numpy on top of the C operator: a small dense Gram system solved by
-``numpy.linalg.solve``.
+The projection onto previous solutions (``Problem.projection``) and flexible
+GMRES (``Problem.gmres``) are written here with numpy on top of the C operator
+(small dense systems solved by ``numpy.linalg``).
 
 Every function cites the passage of the paper it follows; the readings taken
 where the paper is silent or garbled are listed at the top of ``sem_oracle.c``.
@@ -319,6 +319,48 @@ class Problem:
         for ci, xi in zip(c, X):
             x0 += ci * xi
         return x0, b - self.apply(x0)
+
+    def gmres(self, b, rtol=1e-10, restart=30, max_iter=100000, x0=None):
+        """Flexible GMRES(m) with right point-Jacobi preconditioning -- the Krylov solver
+        of the paper's pressure equation (Section 4, Table 2) -- in the unique-node inner
+        product, following Saad, Iterative Methods for Sparse Linear Systems, Alg. 9.6:
+        Arnoldi by modified Gram-Schmidt, the small least-squares problem solved by
+        numpy.linalg.lstsq at every step, restart from the true residual.  Returns
+        (x, {"iters": Arnoldi steps, "cycles": ..., "rel_res": |b - A x| / |b|})."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        norm = lambda v: np.sqrt(self.dot(v, v))
+        bn = norm(b)
+        total, cycles = 0, 0
+        while True:
+            r = b - self.apply(x)
+            beta = norm(r)
+            rel = beta / bn if bn > 0 else 0.0
+            if rel <= rtol or total >= max_iter:
+                break
+            cycles += 1
+            V, Z = [r / beta], []
+            H = np.zeros((restart + 1, restart))
+            y = np.zeros(0)
+            for j in range(restart):
+                z = self.dinv * V[j]
+                Z.append(z)
+                w = self.apply(z)
+                for i in range(j + 1):
+                    H[i, j] = self.dot(w, V[i])
+                    w = w - H[i, j] * V[i]
+                H[j + 1, j] = norm(w)
+                total += 1
+                e1 = np.zeros(j + 2)
+                e1[0] = beta
+                y = np.linalg.lstsq(H[:j + 2, :j + 1], e1, rcond=None)[0]
+                res = np.linalg.norm(e1 - H[:j + 2, :j + 1] @ y)
+                if res <= rtol * bn or total >= max_iter or H[j + 1, j] == 0.0:
+                    break
+                V.append(w / H[j + 1, j])
+            for yi, zi in zip(y, Z):
+                x = x + yi * zi
+        return x, {"iters": total, "cycles": cycles, "rel_res": rel}
 
     def true_rel_res(self, x, b):
         r = b - self.apply(x)

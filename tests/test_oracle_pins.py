@@ -473,3 +473,42 @@ def test_projection_matches_dense_and_is_optimal():
     for _ in range(20):
         y = Xd @ (cd + 0.1 * rng.standard_normal(len(X)) * np.abs(cd).max())
         assert (xs - y) @ A @ (xs - y) >= e0
+
+
+# ------------------------------------------------------------------ GMRES (Section 4, pressure solver)
+def test_gmres_minimal_residual_matches_dense_krylov():
+    """k steps of (unrestarted) right-preconditioned GMRES give the x in
+    x0 + D K_k(A D, r0) (D = point Jacobi) that minimises |b - A x| in the unique-node
+    norm: checked against an explicit Krylov basis and a dense least-squares solve with
+    an independently assembled operator."""
+    P = oracle.Problem(2, 5, 0.05)
+    b = P.assemble_rhs(workloads.uniform(P.n, 3))
+    A, pos, _, _ = brute.assembled(2, 5, 0.05)
+    p_loc = pos[P.glb]
+    free = p_loc >= 0
+    rep = np.array([np.flatnonzero(p_loc == j)[0] for j in range(A.shape[0])])
+    d = P.dinv[rep]
+    bd = b[rep]
+    for k in (1, 3, 6):
+        x, info = P.gmres(b, rtol=1e-30, restart=50, max_iter=k)
+        assert info["iters"] == k
+        K = [bd]
+        for _ in range(k - 1):
+            K.append(A @ (d * K[-1]))
+        Q, _ = np.linalg.qr(np.stack(K, axis=1))   # basis of K_k(A D, b)
+        Y = d[:, None] * Q                          # search space D K_k
+        c = np.linalg.lstsq(A @ Y, bd, rcond=None)[0]
+        xd = Y @ c
+        np.testing.assert_allclose(x[free], xd[p_loc[free]], rtol=0, atol=1e-9 * np.abs(xd).max())
+
+
+def test_gmres_solves_the_system_with_restarts():
+    """Restarted GMRES reaches the tolerance on the true residual and agrees with the
+    CG solution of the same SPD system."""
+    P = oracle.Problem(3, 5, 0.05)
+    b = P.assemble_rhs(workloads.uniform(P.n, 4))
+    x, info = P.gmres(b, rtol=1e-10, restart=10)
+    assert info["cycles"] > 1
+    assert P.true_rel_res(x, b) <= 1e-10
+    xc, _ = P.pcg(b, rtol=1e-13)
+    assert np.abs(x - xc).max() <= 1e-7 * np.abs(xc).max()
