@@ -220,6 +220,28 @@ sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef,
                          sem_space Xh, sem_gs gs, const sem_pcg_params *params,
                          sem_pcg_info *info, void *stream);
 
+/* ---------------------------------------------------------------- GMRES
+ * The paper's pressure equation is solved with GMRES (Section 4, Table 2).
+ * Flexible GMRES(m) (Saad, Algorithm 9.6): right preconditioning with a
+ * preconditioner that may change between steps, Arnoldi in the unique-node inner
+ * product by classical Gram-Schmidt applied twice, Givens rotations, restart after m
+ * steps from the true residual b - A x.  Solves mask QQ^T A_L(h1, h2) x = b for one
+ * field (x, b device FP64, b assembled and masked).  Converged when |b - A x| <= rtol |b|
+ * for the true residual (checked at every restart and at exit).  Device memory:
+ * (2 m + 2) vectors of n_p values, kept by the coef handle between calls. */
+typedef struct {
+    double rtol;      /* > 0, relative to |b|                                          */
+    int max_iter;     /* total Arnoldi steps (>= 1)                                    */
+    int restart;      /* Krylov dimension m of one cycle, 1..200                       */
+    int precond;      /* 0: point Jacobi (the exact assembled diagonal)                 */
+    int use_x0;       /* 1: x holds the initial guess on entry; 0: start from 0         */
+} sem_gmres_params;
+/* info: iters = Arnoldi steps, inner_iters = cycles (restarts + 1), rel_res and
+ * true_rel_res = |b - A x| / |b| at exit.  SEM_ERR_NOT_CONVERGED with x valid when
+ * max_iter is reached first. */
+sem_status sem_gmres_solve(double *x, const double *b, sem_coef coef, sem_mesh msh, sem_space Xh,
+                           sem_gs gs, const sem_gmres_params *params, sem_pcg_info *info, void *stream);
+
 /* ---------------------------------------------------------------- projection space
  * Initial guesses from previous solutions (the paper keeps a space of 20 previous
  * pressure solutions, Section 4 and Table 2, following Nek5000).  The handle holds

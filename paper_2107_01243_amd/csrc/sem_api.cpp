@@ -80,6 +80,7 @@ hipError_t sem_launch_add_f32(double *, const float *, const int *, int64_t, int
 hipError_t sem_launch_dots_finish(const double *, int64_t, int, double *, hipStream_t);
 hipError_t sem_launch_mdot(const MdotArgs *, unsigned, hipStream_t);
 hipError_t sem_launch_comb(const CombArgs *, hipStream_t);
+hipError_t sem_launch_hadamard(double *, const double *, const double *, int64_t, hipStream_t);
 hipError_t sem_launch_residual(double *, const double *, const double *, const double *, int64_t, int,
                                hipStream_t);
 hipError_t sem_launch_fcg_dir(double *, const double *, const double *, const int *, int64_t, int,
@@ -245,6 +246,10 @@ struct Work {
     double *h_fcg = nullptr;        // pinned mirror
     int *done = nullptr;            // device [3]
     int *h_done = nullptr;          // pinned mirror
+    // flexible GMRES: V (m + 1 vectors), Z (m vectors), a work vector; inner products
+    double *gm = nullptr;
+    int gm_m = 0;
+    double *gm_part = nullptr, *gm_out = nullptr, *gm_hout = nullptr;
     RelState *rel = nullptr;        // device [3], reliable-update mixed solve
     RelState *h_rel = nullptr;      // pinned mirror
     void release()
@@ -253,6 +258,10 @@ struct Work {
         dfree(r32); dfree(y32); dfree(p32); dfree(w32); dfree(ri32);
         dfree(partial); dfree(scal); dfree(job64); dfree(job32); dfree(dots); dfree(fcg); dfree(done); dfree(rel);
         dfree(job_cg1); dfree(s);
+        dfree(gm); dfree(gm_part); dfree(gm_out);
+        if (gm_hout) (void)hipHostFree(gm_hout);
+        gm_hout = nullptr;
+        gm_m = 0;
         if (h_rel) (void)hipHostFree(h_rel);
         h_rel = nullptr;
         if (h_scal) (void)hipHostFree(h_scal);
@@ -1515,40 +1524,64 @@ static void proj_free(sem_proj P)
     P->h_out = nullptr;
 }
 
-// host_out[i] = (V_i, v) over unique nodes, i < l (V_i = V + i n)
-static sem_status proj_dots(sem_proj P, const double *V, int l, const double *v, double *host_out, hipStream_t st)
+// Inner products and linear combinations over sets of vectors of n points (the
+// projection space and the Krylov bases): up to PB vectors per pass.
+struct VecCtx {
+    int64_t n;
+    const uint8_t *owner;  // unique-node inner product: one copy of each global id
+    double *partial;       // device [PB][vec grid]
+    double *out;           // device results
+    double *h_out;         // pinned mirror
+};
+
+// host_out[i] = (V_i, v) over unique nodes, i < l (V_i = V + i ld)
+static sem_status vdots(const VecCtx &X, const double *V, int64_t ld, int l, const double *v, double *host_out,
+                        hipStream_t st)
 {
-    const unsigned grid = sem_vec_grid(P->n);
+    const unsigned grid = sem_vec_grid(X.n);
     for (int i0 = 0; i0 < l; i0 += PB) {
-        MdotArgs A{V + (int64_t)i0 * P->n, P->n, std::min(PB, l - i0), v, P->gs->d_owner, P->partial, P->n};
+        MdotArgs A{V + (int64_t)i0 * ld, ld, std::min(PB, l - i0), v, X.owner, X.partial, X.n};
         HIP_TRY(sem_launch_mdot(&A, grid, st));
-        HIP_TRY(sem_launch_dots_finish(P->partial, grid, A.l, P->out + i0, st));
+        HIP_TRY(sem_launch_dots_finish(X.partial, grid, A.l, X.out + i0, st));
     }
-    HIP_TRY(hipMemcpyAsync(P->h_out, P->out, sizeof(double) * l, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(X.h_out, X.out, sizeof(double) * l, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    std::memcpy(host_out, P->h_out, sizeof(double) * l);
+    std::memcpy(host_out, X.h_out, sizeof(double) * l);
     return SEM_OK;
 }
 
 // y = [src +] sum_i c_i V_i (mode 0: y = sum; 1: y += sum; 2: y = src + sum)
-static sem_status proj_comb(sem_proj P, double *y, const double *src, const double *V, int l, const double *c,
-                            int mode, hipStream_t st)
+static sem_status vcomb(const VecCtx &X, double *y, const double *src, const double *V, int64_t ld, int l,
+                        const double *c, int mode, hipStream_t st)
 {
     int i0 = 0;
     do {
         CombArgs A{};
         A.y = y;
         A.src = src;
-        A.V = V + (int64_t)i0 * P->n;
-        A.ld = P->n;
+        A.V = V + (int64_t)i0 * ld;
+        A.ld = ld;
         A.l = std::min(PB, l - i0);
         A.mode = (i0 == 0) ? mode : 1;
         for (int i = 0; i < A.l; ++i) A.c[i] = c[i0 + i];
-        A.n = P->n;
+        A.n = X.n;
         HIP_TRY(sem_launch_comb(&A, st));
         i0 += PB;
     } while (i0 < l);
     return SEM_OK;
+}
+
+static VecCtx proj_ctx(sem_proj P) { return VecCtx{P->n, P->gs->d_owner, P->partial, P->out, P->h_out}; }
+
+static sem_status proj_dots(sem_proj P, const double *V, int l, const double *v, double *host_out, hipStream_t st)
+{
+    return vdots(proj_ctx(P), V, P->n, l, v, host_out, st);
+}
+
+static sem_status proj_comb(sem_proj P, double *y, const double *src, const double *V, int l, const double *c,
+                            int mode, hipStream_t st)
+{
+    return vcomb(proj_ctx(P), y, src, V, P->n, l, c, mode, st);
 }
 
 // w = mask QQ^T A_L d
@@ -1745,6 +1778,152 @@ void sem_proj_destroy(sem_proj proj)
     if (!proj) return;
     proj_free(proj);
     delete proj;
+}
+
+// ------------------------------------------------------------------ flexible GMRES
+static sem_status gmres_apply(sem_coef c, sem_gs g, double *w, const double *z, hipStream_t st)
+{
+    SEM_TRY(launch_ax<double>(c, w, z, 1, st));
+    SEM_TRY(launch_gs<double>(w, 1, g, nullptr, nullptr, st));
+    HIP_TRY(sem_launch_mask(w, 0, c->msh->d_dir_idx, (int64_t)c->msh->dir_idx.size(), c->n, 1, st));
+    return SEM_OK;
+}
+
+// z = M^{-1} v
+static sem_status gmres_precond(sem_coef c, int kind, double *z, const double *v, hipStream_t st)
+{
+    (void)kind;  // 0: point Jacobi
+    HIP_TRY(sem_launch_hadamard(z, c->dinv, v, c->n, st));
+    return SEM_OK;
+}
+
+static sem_status gmres_run(double *x, const double *b, sem_coef c, sem_gs g, const sem_gmres_params *P,
+                            sem_pcg_info *info, hipStream_t st)
+{
+    Work &W = c->ws;
+    const int64_t n = c->n;
+    const int m = P->restart;
+    if (W.gm_m < m) {
+        dfree(W.gm); dfree(W.gm_part); dfree(W.gm_out);
+        if (W.gm_hout) (void)hipHostFree(W.gm_hout);
+        W.gm_hout = nullptr;
+        W.gm_m = 0;
+        SEM_TRY(dalloc(&W.gm, (size_t)(2 * m + 2) * n));
+        SEM_TRY(dalloc(&W.gm_part, (size_t)PB * sem_vec_grid(n)));
+        SEM_TRY(dalloc(&W.gm_out, (size_t)m + 2));
+        HIP_TRY(hipHostMalloc((void **)&W.gm_hout, sizeof(double) * (m + 2), hipHostMallocDefault));
+        W.gm_m = m;
+    }
+    double *V = W.gm;                          // V_0 .. V_m
+    double *Z = W.gm + (int64_t)(m + 1) * n;   // Z_0 .. Z_{m-1}
+    double *wv = Z + (int64_t)m * n;           // work vector
+    const VecCtx X{n, g->d_owner, W.gm_part, W.gm_out, W.gm_hout};
+    double bb;
+    SEM_TRY(vdots(X, b, n, 1, b, &bb, st));
+    const double bn = std::sqrt(bb);
+    if (!P->use_x0) HIP_TRY(sem_launch_fill_f64(x, 0.0, n, st));
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), h(m + 1), h2(m + 1), y(m);
+    int total = 0, cycles = 0;
+    double rel = 0.0;
+    bool breakdown = false;
+    for (;;) {
+        // true residual r = b - A x into V_0 (zero on Dirichlet points)
+        SEM_TRY(gmres_apply(c, g, wv, x, st));
+        HIP_TRY(sem_launch_residual(V, b, wv, c->dinv, n, 1, st));
+        double rr;
+        SEM_TRY(vdots(X, V, n, 1, V, &rr, st));
+        const double beta = std::sqrt(rr);
+        rel = bn > 0.0 ? beta / bn : 0.0;
+        if (!std::isfinite(rel)) { breakdown = true; break; }
+        if (rel <= P->rtol || total >= P->max_iter || breakdown) break;
+        cycles += 1;
+        const double inv = 1.0 / beta;
+        SEM_TRY(vcomb(X, V, nullptr, V, n, 1, &inv, 0, st));
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int jj = 0;
+        for (int j = 0; j < m && total < P->max_iter; ++j) {
+            double *Vj = V + (int64_t)j * n, *Vn = V + (int64_t)(j + 1) * n, *Zj = Z + (int64_t)j * n;
+            SEM_TRY(gmres_precond(c, P->precond, Zj, Vj, st));
+            SEM_TRY(gmres_apply(c, g, Vn, Zj, st));
+            // classical Gram-Schmidt against V_0..V_j, twice
+            SEM_TRY(vdots(X, V, n, j + 1, Vn, h.data(), st));
+            for (int i = 0; i <= j; ++i) h2[i] = -h[i];
+            SEM_TRY(vcomb(X, Vn, nullptr, V, n, j + 1, h2.data(), 1, st));
+            SEM_TRY(vdots(X, V, n, j + 1, Vn, h2.data(), st));
+            for (int i = 0; i <= j; ++i) {
+                h[i] += h2[i];
+                h2[i] = -h2[i];
+            }
+            SEM_TRY(vcomb(X, Vn, nullptr, V, n, j + 1, h2.data(), 1, st));
+            double hh;
+            SEM_TRY(vdots(X, Vn, n, 1, Vn, &hh, st));
+            double hn = std::sqrt(hh);
+            total += 1;
+            jj = j + 1;
+            // rotate column j with the earlier Givens rotations, then annihilate H[j+1][j]
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+                h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+                h[i] = t;
+            }
+            const double den = std::hypot(h[j], hn);
+            if (!(den > 0.0) || !std::isfinite(den)) { breakdown = true; jj = j; break; }
+            cs[j] = h[j] / den;
+            sn[j] = hn / den;
+            h[j] = den;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
+            if (std::fabs(gv[j + 1]) <= P->rtol * bn || hn <= 1e-300) break;  // converged or invariant space
+            const double ih = 1.0 / hn;
+            SEM_TRY(vcomb(X, Vn, nullptr, Vn, n, 1, &ih, 0, st));
+        }
+        if (jj == 0) break;
+        // y = R^{-1} g (upper triangular), x += Z y
+        for (int i = jj - 1; i >= 0; --i) {
+            double sacc = gv[i];
+            for (int k = i + 1; k < jj; ++k) sacc -= H[(size_t)i * m + k] * y[k];
+            y[i] = sacc / H[(size_t)i * m + i];
+        }
+        SEM_TRY(vcomb(X, x, nullptr, Z, n, jj, y.data(), 1, st));
+        if (breakdown) break;
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    const bool conv = !breakdown && rel <= P->rtol;
+    if (info) {
+        info->iters = total;
+        info->inner_iters = cycles;
+        info->converged = conv ? 1 : 0;
+        info->rel_res = rel;
+        info->true_rel_res = rel;
+    }
+    if (breakdown) return fail(SEM_ERR_BREAKDOWN, "GMRES breakdown after %d steps", total);
+    if (!conv) return fail(SEM_ERR_NOT_CONVERGED, "|r|/|b| = %.3e after %d GMRES steps", rel, total);
+    return SEM_OK;
+}
+
+sem_status sem_gmres_solve(double *x, const double *b, sem_coef coef, sem_mesh msh, sem_space Xh, sem_gs gs,
+                           const sem_gmres_params *params, sem_pcg_info *info, void *stream)
+{
+    SEM_TRY(check_coef(coef, msh, Xh));
+    if (!gs || gs->msh != msh) return fail(SEM_ERR_INVALID, "gs is NULL or built for another mesh");
+    if (!params) return fail(SEM_ERR_INVALID, "params is NULL");
+    const sem_gmres_params &P = *params;
+    if (!(P.rtol > 0.0) || !std::isfinite(P.rtol)) return fail(SEM_ERR_INVALID, "rtol must be > 0");
+    if (P.max_iter < 1) return fail(SEM_ERR_INVALID, "max_iter must be >= 1");
+    if (P.restart < 1 || P.restart > 200) return fail(SEM_ERR_INVALID, "restart must be in 1..200");
+    if (P.precond != 0) return fail(SEM_ERR_INVALID, "precond must be 0 (point Jacobi)");
+    const size_t bytes = (size_t)coef->n * 8;
+    if (bytes == 0) return SEM_OK;
+    if (!x || !b) return fail(SEM_ERR_INVALID, "x or b is NULL");
+    if (overlap(x, bytes, b, bytes)) return fail(SEM_ERR_INVALID, "x and b overlap");
+    hipStream_t st = S(stream);
+    SEM_TRY(gs_upload(gs));
+    SEM_TRY(mesh_upload(msh));
+    SEM_TRY(ensure_dinv(coef, gs, st));
+    SEM_TRY(ensure_work(coef, 1, false));
+    return gmres_run(x, b, coef, gs, &P, info, st);
 }
 
 }  // extern "C"

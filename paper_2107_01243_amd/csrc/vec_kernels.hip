@@ -308,6 +308,13 @@ __global__ __launch_bounds__(VT) void k_comb(CombArgs A)
     }
 }
 
+// y = a * b pointwise (point-Jacobi preconditioning of a Krylov vector).
+__global__ __launch_bounds__(VT) void k_hadamard(double *y, const double *a, const double *b, int64_t n)
+{
+    const int64_t t_end = min(n, (int64_t)(blockIdx.x + 1) * CHUNK);
+    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x; t < t_end; t += VT) y[t] = a[t] * b[t];
+}
+
 // STREAM triad a = b + s c (bandwidth micro-benchmark).
 __global__ __launch_bounds__(VT) void k_triad(double *__restrict__ a, const double *__restrict__ b,
                                               const double *__restrict__ c, double s, int64_t n)
@@ -1000,6 +1007,12 @@ hipError_t sem_launch_comb(const CombArgs *A, hipStream_t st)
     if (A->l < 0 || A->l > PB || A->mode < 0 || A->mode > 2) return hipErrorInvalidValue;
     if (A->n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_comb, dim3(stream_grid(A->n)), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_hadamard(double *y, const double *a, const double *b, int64_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hadamard, dim3(stream_grid(n)), dim3(VT), 0, st, y, a, b, n);
     return hipGetLastError();
 }
 hipError_t sem_launch_dots(const DotArgs *A, unsigned grid, hipStream_t st)

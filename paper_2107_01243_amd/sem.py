@@ -36,6 +36,11 @@ class PcgParams(C.Structure):
                 ("use_x0", C.c_int), ("delta", C.c_double), ("variant", C.c_int)]
 
 
+class GmresParams(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("precond", C.c_int),
+                ("use_x0", C.c_int)]
+
+
 class PcgInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("inner_iters", C.c_int), ("converged", C.c_int),
                 ("rel_res", C.c_double), ("true_rel_res", C.c_double)]
@@ -70,6 +75,8 @@ _SIGS = {
     "sem_pcg_solve": ([_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.POINTER(PcgParams),
                        C.POINTER(PcgInfo), _vp], C.c_int),
     "sem_stream_triad": ([_vp, _vp, _vp, C.c_double, C.c_int64, _vp], C.c_int),
+    "sem_gmres_solve": ([_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(GmresParams), C.POINTER(PcgInfo), _vp],
+                        C.c_int),
     "sem_proj_create": ([_vp, _vp, _vp, _vp, C.c_int, C.POINTER(_vp)], C.c_int),
     "sem_proj_size": ([_vp, _vp, _vp, _vp], C.c_int),
     "sem_proj_reset": ([_vp], C.c_int),
@@ -339,6 +346,30 @@ def pcg_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, nfields: int = 1, 
     return out
 
 
+GMRES_PRECOND = {"jacobi": 0}
+
+
+def gmres_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, rtol: float = 1e-10, max_iter: int = 100000,
+                restart: int = 30, precond: str = "jacobi", use_x0: bool = False, stream=None,
+                raise_on_fail: bool = True):
+    """Flexible GMRES(restart) for mask QQ^T A_L x = b (the paper's pressure Krylov
+    solver, Section 4).  Returns an info dict (iters = Arnoldi steps, inner_iters =
+    cycles)."""
+    _dev(x, msh.n, "x")
+    _dev(b, msh.n, "b")
+    if x.dtype != torch.float64 or b.dtype != torch.float64:
+        raise TypeError("x and b must be float64")
+    P = GmresParams(float(rtol), int(max_iter), int(restart), GMRES_PRECOND[precond], int(bool(use_x0)))
+    info = PcgInfo()
+    st = _L.sem_gmres_solve(_ptr(x), _ptr(b), coef._h, msh._h, Xh._h, gs._h, C.byref(P), C.byref(info),
+                            _stream(stream))
+    d = info.as_dict()
+    d["status"] = st
+    if st != SEM_OK and raise_on_fail:
+        raise SemError(st, _L.sem_last_error().decode(errors="replace"))
+    return d
+
+
 class Projection:
     """Space of up to max_vectors previous solutions of one scalar system, used for
     initial guesses (Section 4 and Table 2: 20 previous pressure solutions)."""
@@ -462,6 +493,11 @@ class BoxProblem:
     def adjoint(self, u, v):
         g = torch.empty_like(u)
         return ax_helm_adjoint(g, u, v, self.coef, self.msh, self.Xh)
+
+    def gmres(self, b, **kw):
+        x = torch.zeros_like(b)
+        info = gmres_solve(x, b, self.coef, self.msh, self.Xh, self.gs, **kw)
+        return x, info
 
     def projection(self, max_vectors: int = 20) -> Projection:
         return Projection(self.coef, self.msh, self.Xh, self.gs, max_vectors)

@@ -372,6 +372,49 @@ def test_mixed_three_fields_lx12(mode):
     P.coef.set_helmholtz(1.0, 0.0)
 
 
+# ------------------------------------------------------------------ GMRES (Section 4 pressure solver)
+def test_gmres_fixed_steps_vs_oracle():
+    """k unrestarted GMRES steps are the unique minimal-residual iterate: the GPU's
+    (classical Gram-Schmidt twice) equals the oracle's (modified Gram-Schmidt)."""
+    say("[gmres fixed steps]")
+    P, O = pair(4, 6)
+    P.coef.set_helmholtz(1.0, 0.0)
+    O.set_coef(1.0, 0.0)
+    bl = workloads.uniform(P.n, workloads.SEED_RHS)
+    bo = O.assemble_rhs(bl)
+    b = P.assemble(to_dev(bl))
+    for k in (1, 7, 25):
+        xo, io = O.gmres(bo, rtol=1e-30, restart=60, max_iter=k)
+        x, info = P.gmres(b, rtol=1e-30, restart=60, max_iter=k, raise_on_fail=False)
+        assert info["iters"] == io["iters"] == k
+        say(f"   {k} steps: rel diff {rel_inf(host(x), xo):.2e}, residual {info['rel_res']:.3e} "
+            f"(oracle {io['rel_res']:.3e})")
+        assert rel_inf(host(x), xo) <= 1e-10
+        assert abs(info["rel_res"] - io["rel_res"]) <= 1e-8 * io["rel_res"]
+
+
+@pytest.mark.parametrize("nx,lx,restart", [(4, 6, 20), (3, 8, 40)])
+def test_gmres_to_tolerance(nx, lx, restart):
+    say(f"[gmres rtol] nx={nx} lx={lx} restart={restart}")
+    P, O = pair(nx, lx)
+    P.coef.set_helmholtz(1.0, 0.0)
+    O.set_coef(1.0, 0.0)
+    bl = workloads.uniform(P.n, workloads.SEED_RHS)
+    bo = O.assemble_rhs(bl)
+    b = P.assemble(to_dev(bl))
+    xo, io = O.gmres(bo, rtol=1e-10, restart=restart)
+    x, info = P.gmres(b, rtol=1e-10, restart=restart)
+    say(f"   steps {info['iters']} (oracle {io['iters']}), cycles {info['inner_iters']}")
+    assert abs(info["iters"] - io["iters"]) <= max(2, math.ceil(0.02 * io["iters"]))
+    xh = host(x)
+    tr = O.true_rel_res(xh, bo)
+    assert tr <= 1.05e-10, tr
+    xc, _ = O.pcg(bo, rtol=1e-13)
+    assert rel_inf(xh, xc) <= 1e-7
+    with pytest.raises(sem.SemError, match="INVALID"):
+        P.gmres(b, rtol=1e-10, restart=0)
+
+
 # ------------------------------------------------------------------ projection (Section 4, Table 2)
 def test_projection_sequence_vs_oracle():
     """A sequence of slowly varying loads (two fixed patterns plus 1e-6 noise) solved
