@@ -320,8 +320,124 @@ class Problem:
             x0 += ci * xi
         return x0, b - self.apply(x0)
 
-    def gmres(self, b, rtol=1e-10, restart=30, max_iter=100000, x0=None):
-        """Flexible GMRES(m) with right point-Jacobi preconditioning -- the Krylov solver
+    # -------------------------------------------------------------- two-level Schwarz
+    def schwarz_setup(self, extend=True):
+        """Data of the two-level additive overlapping Schwarz preconditioner of the
+        pressure solve (Section 4: M^{-1} = R0^T A0^{-1} R0 + sum_k Rk^T Ak~^{-1} Rk;
+        coarse grid on linear elements).  Local problem k: element k's lx^3 points with
+        homogeneous Dirichlet conditions one first-GLL-spacing beyond each face; Ak~ is the
+        separable box operator h1 (Mt x Ms x Kr + Mt x Ks x Mr + Kt x Ms x Mr) + h2 Mt x Ms x Mr
+        with, per direction, the element's GLL stiffness and mass for the length
+        L = 2 / sqrt(mean over the element of G_dd / B) plus one linear segment of the
+        first-spacing length at each end (extend=False drops the segments: the element
+        alone, for checks).  Coarse space: trilinear functions of the element vertices;
+        A0 = P^T A P (Galerkin) on the free vertices.  h1, h2 scalars."""
+        if not (np.isscalar(self.h1) and np.isscalar(self.h2)):
+            raise ValueError("the Schwarz preconditioner takes scalar h1, h2")
+        lx, N, E = self.lx, self.lx - 1, self.nelv
+        xi, w, D = self.xi, self.w, self.D
+        Kref = D.T @ np.diag(w) @ D          # 1-D stiffness on [-1, 1]
+        dref = xi[1] - xi[0]                 # first GLL spacing on [-1, 1]
+        G = np.asarray(self.G).reshape(6, E, lx ** 3)
+        B = np.asarray(self.B).reshape(E, lx ** 3)
+        self._loc = []
+        for e in range(E):
+            Ks, Ms = [], []
+            for d in range(3):
+                L = 2.0 / np.sqrt(np.mean(G[d, e] / B[e]))
+                J = L / 2.0
+                K = Kref / J
+                M = np.diag(w * J)
+                if extend:
+                    h = J * dref             # length of each extension segment
+                    K[0, 0] += 1.0 / h
+                    K[N, N] += 1.0 / h
+                    M[0, 0] += h / 2.0
+                    M[N, N] += h / 2.0
+                Ks.append(K)
+                Ms.append(M)
+            # point (i, j, k) at i + lx j + lx^2 k: kron(t, s, r)
+            Kr, Ksd, Kt = Ks
+            Mr, Msd, Mt = Ms
+            A = self.h1 * (np.kron(Mt, np.kron(Msd, Kr)) + np.kron(Mt, np.kron(Ksd, Mr)) +
+                           np.kron(Kt, np.kron(Msd, Mr))) + self.h2 * np.kron(Mt, np.kron(Msd, Mr))
+            self._loc.append(A)
+        # coarse space: vertices = global ids of the element corners
+        corner = [i + lx * (j + lx * k) for k in (0, N) for j in (0, N) for i in (0, N)]
+        cg = np.array([[self.glb[e * lx ** 3 + c] for c in corner] for e in range(E)])
+        vid, cidx = np.unique(cg, return_inverse=True)
+        self._cvert = cidx.reshape(E, 8)
+        nv = len(vid)
+        dirv = np.zeros(nv, bool)
+        for e in range(E):
+            for c in range(8):
+                dirv[self._cvert[e, c]] = self.dirichlet[e * lx ** 3 + corner[c]] != 0
+        self._cfree = ~dirv
+        l0, l1 = (1.0 - xi) / 2.0, (1.0 + xi) / 2.0
+        phi1 = [l0, l1]
+        # phi[c][p]: trilinear basis of corner c = a + 2 b + 4 c at point p of an element
+        self._phi = np.array([np.kron(phi1[cc], np.kron(phi1[bb], phi1[aa]))
+                              for cc in (0, 1) for bb in (0, 1) for aa in (0, 1)])
+        A0 = np.zeros((nv, nv))
+        probes = np.tile(self._phi[:, None, :], (1, E, 1)).reshape(8, -1)
+        for c in range(8):
+            wc = self.ax_local(probes[c]).reshape(E, lx ** 3)
+            for e in range(E):
+                for c2 in range(8):
+                    A0[self._cvert[e, c2], self._cvert[e, c]] += self._phi[c2] @ wc[e]
+        self._A0 = A0
+        return self
+
+    def schwarz_apply(self, r, coarse_iters=10):
+        """z = M^{-1} r for an assembled, masked residual r: the local solves summed over
+        the shared points and averaged by multiplicity, plus the coarse correction P e0,
+        e0 from coarse_iters Jacobi-CG steps on A0 e0 = P^T r (from e0 = 0); masked."""
+        lx, E = self.lx, self.nelv
+        rl = np.asarray(r, dtype=np.float64).reshape(E, lx ** 3)
+        zl = np.stack([np.linalg.solve(self._loc[e], rl[e]) for e in range(E)]).reshape(-1)
+        z = self.gs.op(zl) / self.mult
+        out = z + self.coarse_correction(r, coarse_iters)
+        out[self.dirichlet.astype(bool)] = 0.0
+        return out
+
+    def coarse_correction(self, r, coarse_iters=10):
+        """P e0 with e0 from coarse_iters Jacobi-CG steps on A0 e0 = P^T r, e0 = 0 first."""
+        lx, E = self.lx, self.nelv
+        # r0 = P^T r over unique points (local copies weighted by 1 / mult)
+        rw = (np.asarray(r) / self.mult).reshape(E, lx ** 3)
+        nv = self._A0.shape[0]
+        r0 = np.zeros(nv)
+        for e in range(E):
+            for c in range(8):
+                r0[self._cvert[e, c]] += self._phi[c] @ rw[e]
+        f = self._cfree
+        A0 = self._A0[np.ix_(f, f)]
+        e0 = np.zeros(nv)
+        if coarse_iters > 0 and f.any():
+            bvec = r0[f]
+            dg = 1.0 / np.diag(A0)
+            xk = np.zeros_like(bvec)
+            rk = bvec.copy()
+            zk = dg * rk
+            pk = zk.copy()
+            rz = rk @ zk
+            for _ in range(coarse_iters):
+                if rz == 0.0:
+                    break
+                q = A0 @ pk
+                a = rz / (pk @ q)
+                xk += a * pk
+                rk -= a * q
+                zk = dg * rk
+                rz_new = rk @ zk
+                pk = zk + (rz_new / rz) * pk
+                rz = rz_new
+            e0[f] = xk
+        return np.stack([e0[self._cvert[e]] @ self._phi for e in range(E)]).reshape(-1)
+
+    def gmres(self, b, rtol=1e-10, restart=30, max_iter=100000, x0=None, precond="jacobi", coarse_iters=10):
+        """Flexible GMRES(m) with right preconditioning (point Jacobi, or the two-level
+        Schwarz preconditioner of schwarz_apply) -- the Krylov solver
         of the paper's pressure equation (Section 4, Table 2) -- in the unique-node inner
         product, following Saad, Iterative Methods for Sparse Linear Systems, Alg. 9.6:
         Arnoldi by modified Gram-Schmidt, the small least-squares problem solved by
@@ -343,7 +459,7 @@ class Problem:
             H = np.zeros((restart + 1, restart))
             y = np.zeros(0)
             for j in range(restart):
-                z = self.dinv * V[j]
+                z = self.dinv * V[j] if precond == "jacobi" else self.schwarz_apply(V[j], coarse_iters)
                 Z.append(z)
                 w = self.apply(z)
                 for i in range(j + 1):
