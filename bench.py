@@ -14,9 +14,10 @@ One step = the whole hot path once:
 value = FP64 ax_helm GDOF/s = n_p / (average ax_helm launch time), from HIP events
 on the launch stream over the timed steps.  The JSON line also carries both solve
 times, iteration counts, the roofline of the ax_helm kernel and the CPU oracle
-baseline.  After the timed steps (not part of ms_per_step) a sequence of slowly
-varying loads is solved with a 20-vector projection space (initial guesses from
-previous solutions) and its per-solve iterations and times are reported.
+baseline.  After the timed steps (not part of ms_per_step) the same load is solved
+with the paper's pressure solver (GMRES(30) with the two-level additive Schwarz
+preconditioner), and a sequence of slowly varying loads is solved with a 20-vector
+projection space (initial guesses from previous solutions); both are reported.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -99,6 +100,7 @@ def main():
     ap.add_argument("--reps", type=int, default=20, help="ax_helm launches per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-pressure", action="store_true", help="skip the GMRES + Schwarz solve")
     ap.add_argument("--proj-steps", type=int, default=8,
                     help="solves of the slowly varying load sequence with a 20-vector projection space "
                          "(0: skip)")
@@ -324,6 +326,30 @@ def main():
     for k, (t, bpp) in kern.items():
         log(f"{k}: {t * 1e6:.1f} us, {bpp * P.n / t / 1e9:.0f} GB/s")
 
+    # the paper's pressure solver: GMRES(30) with the two-level additive Schwarz
+    # preconditioner (setup timed separately: host eigen-decompositions and the
+    # Galerkin coarse matrix), on the same load, to the same tolerance
+    pres = None
+    if not a.no_pressure:
+        xg = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sem.schwarz_apply(torch.empty_like(b), b, P.coef, P.msh, P.Xh, P.gs)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t1
+        ts, gi = [], None
+        for _ in range(2):
+            xg.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            gi = sem.gmres_solve(xg, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, restart=30, precond="schwarz")
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        pres = (min(ts), gi, t_setup)
+        log(f"GMRES + two-level Schwarz: {min(ts):.3f}s, {gi['iters']} steps, {gi['inner_iters']} cycles, "
+            f"setup {t_setup:.2f}s")
+        del xg
+
     # projection onto previous solutions: a sequence of slowly varying loads (four
     # fixed patterns with drifting amplitudes, 1e-6 noise), FP64 solves to 1e-10 with a
     # space of 20 previous solutions; the first solve starts from an empty space
@@ -400,6 +426,15 @@ def main():
                                 "frac": round(bpp * P.n / t / 1e9 / HBM_PEAK_GBS, 4)}
                             for k, (t, bpp) in kern.items()}
     out["pcg_fp64_gpoint_iters_per_s"] = round(P.n * out["pcg_fp64_iters"] / out["pcg_fp64_solve_s"] / 1e9, 3)
+    if pres is not None:
+        out.update({
+            "pressure_gmres_schwarz_solve_s": round(pres[0], 4),
+            "pressure_gmres_schwarz_steps": pres[1]["iters"],
+            "pressure_gmres_schwarz_cycles": pres[1]["inner_iters"],
+            "pressure_gmres_schwarz_true_rel_res": pres[1]["true_rel_res"],
+            "pressure_schwarz_setup_s": round(pres[2], 3),
+            "pressure_speedup_vs_jacobi_pcg": round(out["pcg_fp64_solve_s"] / pres[0], 3),
+        })
     if proj_rec:
         warm = proj_rec[4:] if len(proj_rec) > 4 else proj_rec[-1:]
         out.update({

@@ -233,14 +233,37 @@ typedef struct {
     double rtol;      /* > 0, relative to |b|                                          */
     int max_iter;     /* total Arnoldi steps (>= 1)                                    */
     int restart;      /* Krylov dimension m of one cycle, 1..200                       */
-    int precond;      /* 0: point Jacobi (the exact assembled diagonal)                 */
+    int precond;      /* 0: point Jacobi (the exact assembled diagonal); 1: two-level
+                         additive Schwarz (sem_schwarz_apply)                          */
     int use_x0;       /* 1: x holds the initial guess on entry; 0: start from 0         */
+    int coarse_iters; /* precond 1: CG steps of each coarse solve (0 -> 10)             */
 } sem_gmres_params;
 /* info: iters = Arnoldi steps, inner_iters = cycles (restarts + 1), rel_res and
  * true_rel_res = |b - A x| / |b| at exit.  SEM_ERR_NOT_CONVERGED with x valid when
  * max_iter is reached first. */
 sem_status sem_gmres_solve(double *x, const double *b, sem_coef coef, sem_mesh msh, sem_space Xh,
                            sem_gs gs, const sem_gmres_params *params, sem_pcg_info *info, void *stream);
+
+/* z = M0^{-1} r, the two-level additive overlapping Schwarz preconditioner of the
+ * pressure solve (Section 4: M0^{-1} = R0^T A0^{-1} R0 + sum_k Rk^T Ak~^{-1} Rk, coarse grid
+ * on linear elements solved by about ten CG iterations).  Local problem k: element k's
+ * lx^3 points with homogeneous Dirichlet conditions one first-GLL-spacing beyond each
+ * face (neighbouring problems overlap on the shared face points); Ak~ is the separable
+ * box approximation h1 (Mt x Ms x Kr + Mt x Ks x Mr + Kt x Ms x Mr) + h2 Mt x Ms x Mr with,
+ * per direction, the GLL stiffness and mass of the element length
+ * L = 2 / sqrt(mean over the element of G_dd / B) and one linear segment of the first
+ * spacing at each end, inverted by fast diagonalisation.  The local solutions are
+ * summed over shared points (QQ^T) and divided by the multiplicity.  Coarse space:
+ * trilinear functions of the element vertices (the corners' global ids), A0 = P^T A P
+ * (Galerkin) on the free vertices, coarse_iters Jacobi-CG steps from zero (a fixed
+ * count, so the preconditioner varies slightly between applications; GMRES is
+ * flexible).  Needs scalar h1 and h2 (SEM_ERR_UNSUPPORTED otherwise).  r: device FP64,
+ * assembled and masked; z: device FP64, not overlapping r.  The first call for a
+ * (coef, gs) pair builds the data (host eigen-decompositions, eight operator
+ * applications); changing h1 or h2 rebuilds it.  Device memory ~ (3 lx^2 + 3 lx + 8) per
+ * element plus one byte per point, plus the coarse system. */
+sem_status sem_schwarz_apply(double *z, const double *r, sem_coef coef, sem_mesh msh, sem_space Xh,
+                             sem_gs gs, int coarse_iters, void *stream);
 
 /* ---------------------------------------------------------------- projection space
  * Initial guesses from previous solutions (the paper keeps a space of 20 previous

@@ -439,6 +439,72 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DE
     }
 }
 
+// ------------------------------------------------------------------ Schwarz local solves
+// Transform one pencil of the element cube along direction DIR (0: i, 1: j, 2: k):
+// forward out_m = sum_l S[l][m] in_l (S^T), inverse out_l = sum_m S[l][m] in_m (S).
+template <int LX, int DIR, bool FWD>
+__device__ __forceinline__ void fdm_dir(double *cube, const double *S, int t)
+{
+    constexpr int L2 = LX * LX;
+    const int a = t % LX, b = t / LX;
+    const int base = DIR == 0 ? LX * a + L2 * b : (DIR == 1 ? a + L2 * b : a + LX * b);
+    constexpr int stride = DIR == 0 ? 1 : (DIR == 1 ? LX : L2);
+    double in[LX], out[LX];
+#pragma unroll
+    for (int l = 0; l < LX; ++l) in[l] = cube[base + l * stride];
+#pragma unroll
+    for (int m = 0; m < LX; ++m) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < LX; ++l) s = fma(FWD ? S[l * LX + m] : S[m * LX + l], in[l], s);
+        out[m] = s;
+    }
+#pragma unroll
+    for (int l = 0; l < LX; ++l) cube[base + l * stride] = out[l];
+}
+
+// One element per workgroup of lx^2 lanes; the element cube, its three eigenvector
+// matrices and eigenvalues sit in LDS.
+template <int LX>
+__global__ __launch_bounds__(LX * LX) void k_fdm(FdmArgs A)
+{
+    constexpr int L2 = LX * LX, L3 = L2 * LX;
+    __shared__ double cube[L3];
+    __shared__ double S[3][L2];
+    __shared__ double lam[3][LX];
+    const int64_t e = blockIdx.x;
+    const int t = threadIdx.x;
+    const double *Se = A.S + e * 3 * L2;
+    for (int q = t; q < 3 * L2; q += L2) S[q / L2][q % L2] = Se[q];
+    for (int q = t; q < 3 * LX; q += L2) lam[q / LX][q % LX] = A.lam[e * 3 * LX + q];
+    const double *r = A.r + e * L3;
+#pragma unroll
+    for (int k = 0; k < LX; ++k) cube[k * L2 + t] = r[k * L2 + t];
+    __syncthreads();
+    fdm_dir<LX, 0, true>(cube, S[0], t);
+    __syncthreads();
+    fdm_dir<LX, 1, true>(cube, S[1], t);
+    __syncthreads();
+    fdm_dir<LX, 2, true>(cube, S[2], t);
+    __syncthreads();
+    {
+        const int i = t % LX, j = t / LX;
+#pragma unroll
+        for (int k = 0; k < LX; ++k)
+            cube[k * L2 + t] /= A.h1 * (lam[0][i] + lam[1][j] + lam[2][k]) + A.h2;
+    }
+    __syncthreads();
+    fdm_dir<LX, 2, false>(cube, S[2], t);
+    __syncthreads();
+    fdm_dir<LX, 1, false>(cube, S[1], t);
+    __syncthreads();
+    fdm_dir<LX, 0, false>(cube, S[0], t);
+    __syncthreads();
+    double *z = A.z + e * L3;
+#pragma unroll
+    for (int k = 0; k < LX; ++k) z[k * L2 + t] = cube[k * L2 + t];
+}
+
 // ------------------------------------------------------------------ h1-adjoint
 // g = (D v)^T G (D u) per point.
 template <int LX, typename T>
@@ -673,6 +739,13 @@ hipError_t SEM_PASTE(sem_launch_cg1_f64_lx, SEM_LX)(const sem::CgMatvecArgs<doub
                                                      const double *D, int nfields, hipStream_t st)
 {
     return launch_cg<double, true>(*A, D, nfields, st);
+}
+hipError_t SEM_PASTE(sem_launch_fdm_lx, SEM_LX)(const sem::FdmArgs *A, hipStream_t st)
+{
+    if (A->nelv == 0) return hipSuccess;
+    if (A->nelv > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sem::k_fdm<SEM_LX>), dim3((unsigned)A->nelv), dim3(SEM_LX * SEM_LX), 0, st, *A);
+    return hipGetLastError();
 }
 hipError_t SEM_PASTE(sem_launch_adj_f64_lx, SEM_LX)(const sem::AdjArgs<double> *A, const double *D,
                                                      hipStream_t st)

@@ -43,6 +43,7 @@ using namespace sem;
                                                   hipStream_t);                                             \
     extern "C" hipError_t sem_launch_cg1_f64_lx##L(const CgMatvecArgs<double> *, const double *, int,       \
                                                    hipStream_t);                                            \
+    extern "C" hipError_t sem_launch_fdm_lx##L(const FdmArgs *, hipStream_t);                               \
     extern "C" hipError_t sem_launch_adj_f64_lx##L(const AdjArgs<double> *, const double *, hipStream_t);   \
     extern "C" hipError_t sem_launch_adj_f32_lx##L(const AdjArgs<float> *, const double *, hipStream_t);    \
     extern "C" hipError_t sem_launch_geom_lx##L(const GeomArgs *, const double *, const double *,           \
@@ -81,6 +82,11 @@ hipError_t sem_launch_dots_finish(const double *, int64_t, int, double *, hipStr
 hipError_t sem_launch_mdot(const MdotArgs *, unsigned, hipStream_t);
 hipError_t sem_launch_comb(const CombArgs *, hipStream_t);
 hipError_t sem_launch_hadamard(double *, const double *, const double *, int64_t, hipStream_t);
+hipError_t sem_launch_corner(const CornerArgs *, hipStream_t);
+hipError_t sem_launch_vgather(const VGatherArgs *, hipStream_t);
+hipError_t sem_launch_coarse_cg(const CoarseArgs *, int, hipStream_t);
+hipError_t sem_launch_prolong(const ProlongArgs *, hipStream_t);
+hipError_t sem_launch_probe(double *, const double *, int, int64_t, int, hipStream_t);
 hipError_t sem_launch_residual(double *, const double *, const double *, const double *, int64_t, int,
                                hipStream_t);
 hipError_t sem_launch_fcg_dir(double *, const double *, const double *, const int *, int64_t, int,
@@ -100,6 +106,7 @@ struct LxFns {
     hipError_t (*cg64)(const CgMatvecArgs<double> *, const double *, int, hipStream_t);
     hipError_t (*cg32)(const CgMatvecArgs<float> *, const double *, int, hipStream_t);
     hipError_t (*cg1)(const CgMatvecArgs<double> *, const double *, int, hipStream_t);
+    hipError_t (*fdm)(const FdmArgs *, hipStream_t);
     hipError_t (*adj64)(const AdjArgs<double> *, const double *, hipStream_t);
     hipError_t (*adj32)(const AdjArgs<float> *, const double *, hipStream_t);
     hipError_t (*geom)(const GeomArgs *, const double *, const double *, hipStream_t);
@@ -112,7 +119,7 @@ const LxFns &fns(int lx)
 {
 #define SEM_ROW(L)                                                                                 \
     {sem_launch_ax_f64_lx##L, sem_launch_ax_f32_lx##L, sem_launch_cg_f64_lx##L, sem_launch_cg_f32_lx##L, \
-     sem_launch_cg1_f64_lx##L,                                                                     \
+     sem_launch_cg1_f64_lx##L, sem_launch_fdm_lx##L,                                               \
      sem_launch_adj_f64_lx##L, sem_launch_adj_f32_lx##L, sem_launch_geom_lx##L, sem_launch_diag_lx##L,  \
      sem_cg_nblocks_f64_lx##L, sem_cg_nblocks_f32_lx##L},
     static const LxFns table[] = {SEM_LX_LIST(SEM_ROW)};
@@ -275,6 +282,37 @@ struct Work {
 
 }  // namespace
 
+// Two-level additive Schwarz preconditioner data, built on first use for a (coef, gs)
+// pair and dropped when the Helmholtz coefficients change.
+struct SchwarzData {
+    bool valid = false;
+    const void *gs = nullptr;
+    double *S = nullptr, *lam = nullptr;  // [nelv][3][lx][lx], [nelv][3][lx]
+    double *phi = nullptr;                // [8][lx^3]
+    int32_t *cvert = nullptr;             // [nelv][8]
+    int64_t nv = 0;
+    int64_t *v_ptr = nullptr;
+    int32_t *v_idx = nullptr;
+    uint8_t *v_dir = nullptr;
+    int64_t *rp = nullptr;
+    int32_t *ci = nullptr;
+    double *val = nullptr, *dinv0 = nullptr;
+    double *part = nullptr;               // [nelv * 8]
+    double *cv = nullptr;                 // [6][nv]: b0, x, r, z, p, q
+    double *cpart = nullptr;              // [2][ceil(nv / 256)]
+    double *cscal = nullptr;              // [4]
+    uint8_t *mult = nullptr;              // [n]
+    void release()
+    {
+        dfree(S); dfree(lam); dfree(phi); dfree(cvert); dfree(v_ptr); dfree(v_idx); dfree(v_dir);
+        dfree(rp); dfree(ci); dfree(val); dfree(dinv0); dfree(part); dfree(cv); dfree(cpart); dfree(cscal);
+        dfree(mult);
+        valid = false;
+        gs = nullptr;
+        nv = 0;
+    }
+};
+
 struct sem_coef_s {
     sem_space Xh = nullptr;
     sem_mesh msh = nullptr;
@@ -292,6 +330,7 @@ struct sem_coef_s {
     bool dinv_valid = false;
     const void *dinv_gs = nullptr;
     Work ws;
+    SchwarzData sz;
 };
 
 // ------------------------------------------------------------------ small helpers
@@ -957,6 +996,7 @@ sem_status sem_coef_set_helmholtz(sem_coef c, const double *h1_dev, double h1, c
         c->h2s = h2;
     }
     c->dinv_valid = false;
+    c->sz.valid = false;
     return SEM_OK;
 }
 
@@ -974,6 +1014,7 @@ void sem_coef_destroy(sem_coef c)
 {
     if (!c) return;
     c->ws.release();
+    c->sz.release();
     dfree(c->G); dfree(c->B); dfree(c->G32); dfree(c->B32);
     dfree(c->h1); dfree(c->h2); dfree(c->h1_32); dfree(c->h2_32);
     dfree(c->dinv); dfree(c->dinv32);
@@ -1780,6 +1821,219 @@ void sem_proj_destroy(sem_proj proj)
     delete proj;
 }
 
+// ------------------------------------------------------------------ two-level Schwarz
+// Setup (host + a few launches): element lengths from the geometric factors, the
+// 1-D extended operators and their eigen-decompositions, the coarse vertices and
+// the Galerkin coarse matrix from eight probe applications of A_L.
+static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
+{
+    SchwarzData &Z = c->sz;
+    if (Z.valid && Z.gs == (const void *)g) return SEM_OK;
+    if (c->h1 || c->h2) return fail(SEM_ERR_UNSUPPORTED, "the Schwarz preconditioner needs scalar h1 and h2");
+    Z.release();
+    const int lx = c->lx, N = lx - 1, lx3 = lx * lx * lx;
+    const int64_t E = c->nelv, n = c->n;
+    const sem_space Xh = c->Xh;
+    // element lengths: L_d = 2 / sqrt(mean over the element of G_dd / B)
+    std::vector<double> G((size_t)3 * n), B(n);
+    HIP_TRY(hipMemcpy(G.data(), c->G, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(B.data(), c->B, sizeof(double) * n, hipMemcpyDeviceToHost));
+    std::vector<double> Kref((size_t)lx * lx, 0.0);
+    for (int m = 0; m < lx; ++m)
+        for (int q = 0; q < lx; ++q)
+            for (int i = 0; i < lx; ++i) Kref[m * lx + q] += Xh->w[i] * Xh->D[i * lx + m] * Xh->D[i * lx + q];
+    const double dref = Xh->xi[1] - Xh->xi[0];
+    std::vector<double> S((size_t)E * 3 * lx * lx), lam((size_t)E * 3 * lx);
+    semh::parallel_for(E, [&](int64_t e0, int64_t e1) {
+        std::vector<double> a((size_t)lx * lx), V((size_t)lx * lx), l(lx), M(lx);
+        for (int64_t e = e0; e < e1; ++e) {
+            for (int d = 0; d < 3; ++d) {
+                double sum = 0.0;
+                for (int p = 0; p < lx3; ++p) sum += G[(size_t)d * n + e * lx3 + p] / B[e * lx3 + p];
+                const double L = 2.0 / std::sqrt(sum / lx3), J = L / 2.0, h = J * dref;
+                for (int i = 0; i < lx; ++i) M[i] = Xh->w[i] * J;
+                M[0] += h / 2.0;
+                M[N] += h / 2.0;
+                // C = M^{-1/2} K M^{-1/2}, K = Kref / J + 1/h on the two face diagonals
+                for (int i = 0; i < lx; ++i)
+                    for (int q = 0; q < lx; ++q) {
+                        double k = Kref[i * lx + q] / J;
+                        if (i == q && (i == 0 || i == N)) k += 1.0 / h;
+                        a[i * lx + q] = k / std::sqrt(M[i] * M[q]);
+                    }
+                semh::sym_eig(lx, a.data(), V.data(), l.data());
+                double *Sd = &S[((size_t)e * 3 + d) * lx * lx];
+                for (int i = 0; i < lx; ++i)
+                    for (int m = 0; m < lx; ++m) Sd[i * lx + m] = V[i * lx + m] / std::sqrt(M[i]);
+                for (int m = 0; m < lx; ++m) lam[((size_t)e * 3 + d) * lx + m] = l[m];
+            }
+        }
+    });
+    // trilinear corner functions at the GLL points, corner c = a + 2 b + 4 cc
+    std::vector<double> phi((size_t)8 * lx3);
+    for (int cc = 0; cc < 2; ++cc)
+        for (int bb = 0; bb < 2; ++bb)
+            for (int aa = 0; aa < 2; ++aa) {
+                const int c8 = aa + 2 * bb + 4 * cc;
+                auto l1 = [&](int side, int i) { return side ? (1.0 + Xh->xi[i]) / 2.0 : (1.0 - Xh->xi[i]) / 2.0; };
+                for (int k = 0; k < lx; ++k)
+                    for (int j = 0; j < lx; ++j)
+                        for (int i = 0; i < lx; ++i)
+                            phi[(size_t)c8 * lx3 + i + lx * (j + lx * k)] = l1(aa, i) * l1(bb, j) * l1(cc, k);
+            }
+    // coarse vertices: the global ids of the element corners
+    const sem_mesh msh = c->msh;
+    std::vector<int64_t> cg((size_t)E * 8);
+    int corner[8];
+    for (int c8 = 0; c8 < 8; ++c8) {
+        const int i = (c8 & 1) ? N : 0, j = (c8 & 2) ? N : 0, k = (c8 & 4) ? N : 0;
+        corner[c8] = i + lx * (j + lx * k);
+    }
+    for (int64_t e = 0; e < E; ++e)
+        for (int c8 = 0; c8 < 8; ++c8) cg[e * 8 + c8] = msh->glb[e * lx3 + corner[c8]];
+    std::vector<int64_t> vid(cg);
+    std::sort(vid.begin(), vid.end());
+    vid.erase(std::unique(vid.begin(), vid.end()), vid.end());
+    const int64_t nv = (int64_t)vid.size();
+    std::vector<int32_t> cvert((size_t)E * 8);
+    std::vector<uint8_t> vdir(nv, 0);
+    for (int64_t q = 0; q < E * 8; ++q) {
+        cvert[q] = (int32_t)(std::lower_bound(vid.begin(), vid.end(), cg[q]) - vid.begin());
+        const int64_t e = q / 8;
+        if (!msh->dir.empty() && msh->dir[e * lx3 + corner[q % 8]]) vdir[cvert[q]] = 1;
+    }
+    std::vector<int64_t> vptr(nv + 1, 0);
+    for (int64_t q = 0; q < E * 8; ++q) vptr[cvert[q] + 1] += 1;
+    for (int64_t v = 0; v < nv; ++v) vptr[v + 1] += vptr[v];
+    std::vector<int32_t> vidx(E * 8);
+    {
+        std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
+        for (int64_t q = 0; q < E * 8; ++q) vidx[fill[cvert[q]]++] = (int32_t)q;  // ascending e
+    }
+    // device data
+    SEM_TRY(dalloc(&Z.S, S.size()));
+    SEM_TRY(dalloc(&Z.lam, lam.size()));
+    SEM_TRY(dalloc(&Z.phi, phi.size()));
+    SEM_TRY(dalloc(&Z.cvert, cvert.size()));
+    SEM_TRY(dalloc(&Z.v_ptr, vptr.size()));
+    SEM_TRY(dalloc(&Z.v_idx, vidx.size()));
+    SEM_TRY(dalloc(&Z.v_dir, vdir.size()));
+    SEM_TRY(dalloc(&Z.part, (size_t)E * 8));
+    SEM_TRY(dalloc(&Z.mult, (size_t)n));
+    HIP_TRY(hipMemcpy(Z.S, S.data(), S.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(Z.lam, lam.data(), lam.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(Z.phi, phi.data(), phi.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(Z.cvert, cvert.data(), cvert.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(Z.v_ptr, vptr.data(), vptr.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(Z.v_idx, vidx.data(), vidx.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(Z.v_dir, vdir.data(), vdir.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(Z.mult, g->m.mult.data(), (size_t)n, hipMemcpyHostToDevice));
+    // Galerkin coarse matrix: element blocks A0_e[c'][c] = phi_c'^T A_L phi_c from probes
+    SEM_TRY(ensure_work(c, 1, false));
+    Work &W = c->ws;
+    std::vector<double> Ae((size_t)E * 64), pe((size_t)E * 8);
+    for (int c8 = 0; c8 < 8; ++c8) {
+        HIP_TRY(sem_launch_probe(W.r, Z.phi, c8, E, lx3, st));
+        SEM_TRY(launch_ax<double>(c, W.w, W.r, 1, st));
+        CornerArgs CA{W.w, nullptr, Z.phi, Z.part, E, lx3};
+        HIP_TRY(sem_launch_corner(&CA, st));
+        HIP_TRY(hipMemcpyAsync(pe.data(), Z.part, sizeof(double) * E * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int64_t e = 0; e < E; ++e)
+            for (int c2 = 0; c2 < 8; ++c2) Ae[(size_t)e * 64 + c2 * 8 + c8] = pe[e * 8 + c2];
+    }
+    // assemble: rows ascending, columns ascending, duplicates summed in element order;
+    // Dirichlet vertices keep an identity row
+    struct Tri { int64_t r, c, e; double v; };
+    std::vector<Tri> tri;
+    tri.reserve((size_t)E * 64 + nv);
+    for (int64_t e = 0; e < E; ++e)
+        for (int c2 = 0; c2 < 8; ++c2)
+            for (int c8 = 0; c8 < 8; ++c8) {
+                const int64_t r = cvert[e * 8 + c2], cc = cvert[e * 8 + c8];
+                if (vdir[r] || vdir[cc]) continue;
+                tri.push_back({r, cc, e, Ae[(size_t)e * 64 + c2 * 8 + c8]});
+            }
+    for (int64_t v = 0; v < nv; ++v)
+        if (vdir[v]) tri.push_back({v, v, -1, 1.0});
+    std::sort(tri.begin(), tri.end(), [](const Tri &a, const Tri &b) {
+        return a.r != b.r ? a.r < b.r : (a.c != b.c ? a.c < b.c : a.e < b.e);
+    });
+    std::vector<int64_t> rp(nv + 1, 0);
+    std::vector<int32_t> ci;
+    std::vector<double> val, dg(nv, 1.0);
+    for (size_t q = 0; q < tri.size();) {
+        size_t q2 = q;
+        double sum = 0.0;
+        while (q2 < tri.size() && tri[q2].r == tri[q].r && tri[q2].c == tri[q].c) sum += tri[q2++].v;
+        ci.push_back((int32_t)tri[q].c);
+        val.push_back(sum);
+        rp[tri[q].r + 1] += 1;
+        if (tri[q].r == tri[q].c) dg[tri[q].r] = sum;
+        q = q2;
+    }
+    for (int64_t v = 0; v < nv; ++v) rp[v + 1] += rp[v];
+    for (double &d : dg) d = (d != 0.0) ? 1.0 / d : 0.0;
+    SEM_TRY(dalloc(&Z.rp, rp.size()));
+    SEM_TRY(dalloc(&Z.ci, std::max<size_t>(ci.size(), 1)));
+    SEM_TRY(dalloc(&Z.val, std::max<size_t>(val.size(), 1)));
+    SEM_TRY(dalloc(&Z.dinv0, (size_t)nv));
+    SEM_TRY(dalloc(&Z.cv, (size_t)6 * nv));
+    SEM_TRY(dalloc(&Z.cpart, (size_t)2 * ((nv + 255) / 256)));
+    SEM_TRY(dalloc(&Z.cscal, 4));
+    HIP_TRY(hipMemcpy(Z.rp, rp.data(), rp.size() * 8, hipMemcpyHostToDevice));
+    if (!ci.empty()) {
+        HIP_TRY(hipMemcpy(Z.ci, ci.data(), ci.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(Z.val, val.data(), val.size() * 8, hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMemcpy(Z.dinv0, dg.data(), dg.size() * 8, hipMemcpyHostToDevice));
+    Z.nv = nv;
+    Z.gs = g;
+    Z.valid = true;
+    return SEM_OK;
+}
+
+// z = M^{-1} r: local solves summed over shared points and averaged, plus P e0 from
+// coarse_iters Jacobi-CG steps on A0 e0 = P^T r; masked.  r assembled and masked.
+static sem_status schwarz_apply(sem_coef c, sem_gs g, double *z, const double *r, int coarse_iters, hipStream_t st)
+{
+    SchwarzData &Z = c->sz;
+    const int lx = c->lx, lx3 = lx * lx * lx;
+    const FdmArgs F{z, r, Z.S, Z.lam, c->h1s, c->h2s, c->nelv};
+    HIP_TRY(fns(lx).fdm(&F, st));
+    SEM_TRY(launch_gs<double>(z, 1, g, nullptr, nullptr, st));
+    const CornerArgs CA{r, g->d_owner, Z.phi, Z.part, c->nelv, lx3};
+    HIP_TRY(sem_launch_corner(&CA, st));
+    const int64_t nv = Z.nv;
+    double *b0 = Z.cv, *x0 = Z.cv + nv;
+    const VGatherArgs VA{b0, Z.part, Z.v_ptr, Z.v_idx, Z.v_dir, nv};
+    HIP_TRY(sem_launch_vgather(&VA, st));
+    const CoarseArgs CC{Z.rp, Z.ci, Z.val, Z.dinv0, b0, x0, Z.cv + 2 * nv, Z.cv + 3 * nv, Z.cv + 4 * nv,
+                        Z.cv + 5 * nv, Z.cpart, Z.cscal, nv};
+    HIP_TRY(sem_launch_coarse_cg(&CC, coarse_iters, st));
+    const ProlongArgs PA{z, Z.mult, Z.phi, x0, Z.cvert, c->nelv, lx3};
+    HIP_TRY(sem_launch_prolong(&PA, st));
+    HIP_TRY(sem_launch_mask(z, 0, c->msh->d_dir_idx, (int64_t)c->msh->dir_idx.size(), c->n, 1, st));
+    return SEM_OK;
+}
+
+sem_status sem_schwarz_apply(double *z, const double *r, sem_coef coef, sem_mesh msh, sem_space Xh, sem_gs gs,
+                             int coarse_iters, void *stream)
+{
+    SEM_TRY(check_coef(coef, msh, Xh));
+    if (!gs || gs->msh != msh) return fail(SEM_ERR_INVALID, "gs is NULL or built for another mesh");
+    if (coarse_iters < 0 || coarse_iters > 10000) return fail(SEM_ERR_INVALID, "coarse_iters must be in 0..10000");
+    const size_t bytes = (size_t)coef->n * 8;
+    if (bytes == 0) return SEM_OK;
+    if (!z || !r) return fail(SEM_ERR_INVALID, "z or r is NULL");
+    if (overlap(z, bytes, r, bytes)) return fail(SEM_ERR_INVALID, "z and r overlap");
+    hipStream_t st = S(stream);
+    SEM_TRY(gs_upload(gs));
+    SEM_TRY(mesh_upload(msh));
+    SEM_TRY(schwarz_setup(coef, gs, st));
+    return schwarz_apply(coef, gs, z, r, coarse_iters, st);
+}
+
 // ------------------------------------------------------------------ flexible GMRES
 static sem_status gmres_apply(sem_coef c, sem_gs g, double *w, const double *z, hipStream_t st)
 {
@@ -1789,10 +2043,11 @@ static sem_status gmres_apply(sem_coef c, sem_gs g, double *w, const double *z, 
     return SEM_OK;
 }
 
-// z = M^{-1} v
-static sem_status gmres_precond(sem_coef c, int kind, double *z, const double *v, hipStream_t st)
+// z = M^{-1} v (0: point Jacobi; 1: two-level Schwarz)
+static sem_status gmres_precond(sem_coef c, sem_gs g, const sem_gmres_params *P, double *z, const double *v,
+                                hipStream_t st)
 {
-    (void)kind;  // 0: point Jacobi
+    if (P->precond == 1) return schwarz_apply(c, g, z, v, P->coarse_iters > 0 ? P->coarse_iters : 10, st);
     HIP_TRY(sem_launch_hadamard(z, c->dinv, v, c->n, st));
     return SEM_OK;
 }
@@ -1844,7 +2099,7 @@ static sem_status gmres_run(double *x, const double *b, sem_coef c, sem_gs g, co
         int jj = 0;
         for (int j = 0; j < m && total < P->max_iter; ++j) {
             double *Vj = V + (int64_t)j * n, *Vn = V + (int64_t)(j + 1) * n, *Zj = Z + (int64_t)j * n;
-            SEM_TRY(gmres_precond(c, P->precond, Zj, Vj, st));
+            SEM_TRY(gmres_precond(c, g, P, Zj, Vj, st));
             SEM_TRY(gmres_apply(c, g, Vn, Zj, st));
             // classical Gram-Schmidt against V_0..V_j, twice
             SEM_TRY(vdots(X, V, n, j + 1, Vn, h.data(), st));
@@ -1913,7 +2168,8 @@ sem_status sem_gmres_solve(double *x, const double *b, sem_coef coef, sem_mesh m
     if (!(P.rtol > 0.0) || !std::isfinite(P.rtol)) return fail(SEM_ERR_INVALID, "rtol must be > 0");
     if (P.max_iter < 1) return fail(SEM_ERR_INVALID, "max_iter must be >= 1");
     if (P.restart < 1 || P.restart > 200) return fail(SEM_ERR_INVALID, "restart must be in 1..200");
-    if (P.precond != 0) return fail(SEM_ERR_INVALID, "precond must be 0 (point Jacobi)");
+    if (P.precond != 0 && P.precond != 1) return fail(SEM_ERR_INVALID, "precond must be 0 or 1");
+    if (P.coarse_iters < 0 || P.coarse_iters > 10000) return fail(SEM_ERR_INVALID, "coarse_iters must be in 0..10000");
     const size_t bytes = (size_t)coef->n * 8;
     if (bytes == 0) return SEM_OK;
     if (!x || !b) return fail(SEM_ERR_INVALID, "x or b is NULL");
@@ -1923,6 +2179,7 @@ sem_status sem_gmres_solve(double *x, const double *b, sem_coef coef, sem_mesh m
     SEM_TRY(mesh_upload(msh));
     SEM_TRY(ensure_dinv(coef, gs, st));
     SEM_TRY(ensure_work(coef, 1, false));
+    if (P.precond == 1) SEM_TRY(schwarz_setup(coef, gs, st));
     return gmres_run(x, b, coef, gs, &P, info, st);
 }
 

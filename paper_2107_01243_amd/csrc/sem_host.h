@@ -36,4 +36,8 @@ bool build_gs_maps(int64_t n, const int64_t *glb, const uint8_t *dir, GsMaps &m,
 void element_order(const GsMaps &m, std::vector<int32_t> &pairs, std::vector<int64_t> &blk_ptr,
                    std::vector<int32_t> &blk_idx);
 
+// Symmetric eigen-decomposition a = V diag(lam) V^T of the n x n row-major matrix a
+// (destroyed) by cyclic Jacobi rotations; V row-major [row][mode].
+void sym_eig(int n, double *a, double *V, double *lam);
+
 }  // namespace semh

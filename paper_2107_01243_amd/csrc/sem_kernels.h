@@ -114,4 +114,17 @@ struct DiagArgs {
     int64_t n;
 };
 
+// Local solves of the two-level Schwarz preconditioner (fast diagonalisation):
+// z_e = (S_t x S_s x S_r) diag(1 / (h1 (lr_i + ls_j + lt_k) + h2)) (S_t x S_s x S_r)^T r_e,
+// with per element and direction the eigenvectors S (row-major [point][mode]) and
+// eigenvalues of the 1-D generalised problem K S = M S Lambda.
+struct FdmArgs {
+    double *z;          // [nelv][lx^3]
+    const double *r;    // [nelv][lx^3]
+    const double *S;    // [nelv][3][lx][lx]
+    const double *lam;  // [nelv][3][lx]
+    double h1, h2;
+    int64_t nelv;
+};
+
 }  // namespace sem

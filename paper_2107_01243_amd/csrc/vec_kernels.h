@@ -156,4 +156,49 @@ struct CombArgs {
     int64_t n;
 };
 
+// ---------------------------------------------------------------- two-level Schwarz
+// out[e][c] = sum over element e's points p of phi[c][p] v[e][p] (owner[p] if owner).
+struct CornerArgs {
+    const double *v;
+    const uint8_t *owner;  // nullptr: every point counts
+    const double *phi;     // [8][lx^3] trilinear basis at the GLL points
+    double *out;           // [nelv][8]
+    int64_t nelv;
+    int lx3;
+};
+
+// Coarse vector from the corner sums: b0[v] = sum over (e, c) at vertex v, ascending e.
+struct VGatherArgs {
+    double *b0;
+    const double *part;    // [nelv * 8]
+    const int64_t *ptr;    // [nv + 1]
+    const int32_t *idx;    // e * 8 + c
+    const uint8_t *dir;    // [nv] Dirichlet vertex (b0 = 0)
+    int64_t nv;
+};
+
+// Fixed-count Jacobi-CG on the coarse CSR matrix (Dirichlet vertices: identity rows).
+struct CoarseArgs {
+    const int64_t *rp;
+    const int32_t *ci;
+    const double *val;
+    const double *dinv;
+    const double *b;
+    double *x, *r, *z, *p, *q;
+    double *partial;       // [2][grid]
+    double *scal;          // [4]: rz, pq, alpha, beta
+    int64_t nv;
+};
+
+// z = z / mult + sum_c phi[c][p] e0[cvert[e][c]]
+struct ProlongArgs {
+    double *z;
+    const uint8_t *mult;
+    const double *phi;
+    const double *e0;
+    const int32_t *cvert;  // [nelv][8]
+    int64_t nelv;
+    int lx3;
+};
+
 }  // namespace sem

@@ -315,6 +315,171 @@ __global__ __launch_bounds__(VT) void k_hadamard(double *y, const double *a, con
     for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x; t < t_end; t += VT) y[t] = a[t] * b[t];
 }
 
+// ------------------------------------------------------------------ two-level Schwarz
+// Per element, the eight weighted sums against the trilinear corner functions (the
+// restriction R0 = P^T, and the Galerkin products P_e^T A_e P_e from probe vectors).
+__global__ __launch_bounds__(VT) void k_corner(CornerArgs A)
+{
+    __shared__ double sh[8][VT / 64];
+    const int64_t e = blockIdx.x;
+    double acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    for (int p = threadIdx.x; p < A.lx3; p += VT) {
+        const int64_t t = e * A.lx3 + p;
+        const double x = (A.owner && !A.owner[t]) ? 0.0 : A.v[t];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = fma(A.phi[c * A.lx3 + p], x, acc[c]);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        double x = acc[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) sh[c][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double x = 0.0;
+#pragma unroll
+        for (int q = 0; q < VT / 64; ++q) x += sh[threadIdx.x][q];
+        A.out[e * 8 + threadIdx.x] = x;
+    }
+}
+
+__global__ __launch_bounds__(VT) void k_vgather(VGatherArgs A)
+{
+    const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (v >= A.nv) return;
+    double s = 0.0;
+    if (!A.dir[v])
+        for (int64_t q = A.ptr[v]; q < A.ptr[v + 1]; ++q) s += A.part[A.idx[q]];
+    A.b0[v] = s;
+}
+
+// Coarse Jacobi-CG: start (x = 0, r = b, z = D r, p = z, partial of r.z).
+__global__ __launch_bounds__(VT) void k_ccg_start(CoarseArgs A)
+{
+    __shared__ double sh[VT / 64];
+    const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
+    double rz = 0.0;
+    if (v < A.nv) {
+        const double rv = A.b[v], zv = A.dinv[v] * rv;
+        A.x[v] = 0.0;
+        A.r[v] = rv;
+        A.z[v] = zv;
+        A.p[v] = zv;
+        rz = rv * zv;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rz += __shfl_xor(rz, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = rz;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < VT / 64; ++q) s += sh[q];
+        A.partial[blockIdx.x] = s;
+    }
+}
+
+// q = A p, partial of p.q
+__global__ __launch_bounds__(VT) void k_ccg_spmv(CoarseArgs A)
+{
+    __shared__ double sh[VT / 64];
+    const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
+    double pq = 0.0;
+    if (v < A.nv) {
+        double s = 0.0;
+        for (int64_t k = A.rp[v]; k < A.rp[v + 1]; ++k) s = fma(A.val[k], A.p[A.ci[k]], s);
+        A.q[v] = s;
+        pq = A.p[v] * s;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) pq += __shfl_xor(pq, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = pq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < VT / 64; ++q) s += sh[q];
+        A.partial[gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// Single workgroup: which = 0 sets rz from partial[0..nblk) (start); 1 sets alpha =
+// rz / pq from partial[nblk..2nblk); 2 sets beta = rz_new / rz, rz = rz_new.
+__global__ __launch_bounds__(RT) void k_ccg_scalar(CoarseArgs A, int64_t nblk, int which)
+{
+    __shared__ double sh[RT];
+    const double s = block_sum_fixed<RT>(A.partial + (which == 1 ? nblk : 0), nblk, sh);
+    if (threadIdx.x == 0) {
+        if (which == 0) {
+            A.scal[0] = s;
+        } else if (which == 1) {
+            A.scal[2] = (s > 0.0 && isfinite(s)) ? A.scal[0] / s : 0.0;
+        } else {
+            A.scal[3] = (A.scal[0] != 0.0) ? s / A.scal[0] : 0.0;
+            A.scal[0] = s;
+        }
+    }
+}
+
+// x += alpha p; r -= alpha q; z = D r; partial of r.z
+__global__ __launch_bounds__(VT) void k_ccg_update(CoarseArgs A)
+{
+    __shared__ double sh[VT / 64];
+    const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
+    const double alpha = A.scal[2];
+    double rz = 0.0;
+    if (v < A.nv) {
+        A.x[v] = fma(alpha, A.p[v], A.x[v]);
+        const double rv = fma(-alpha, A.q[v], A.r[v]);
+        A.r[v] = rv;
+        const double zv = A.dinv[v] * rv;
+        A.z[v] = zv;
+        rz = rv * zv;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rz += __shfl_xor(rz, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = rz;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < VT / 64; ++q) s += sh[q];
+        A.partial[blockIdx.x] = s;
+    }
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(VT) void k_ccg_dir(CoarseArgs A)
+{
+    const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (v < A.nv) A.p[v] = fma(A.scal[3], A.p[v], A.z[v]);
+}
+
+__global__ __launch_bounds__(VT) void k_prolong(ProlongArgs A)
+{
+    const int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (t >= A.nelv * A.lx3) return;
+    const int64_t e = t / A.lx3;
+    const int p = (int)(t - e * A.lx3);
+    double s = A.z[t] / (double)A.mult[t];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s = fma(A.phi[c * A.lx3 + p], A.e0[A.cvert[e * 8 + c]], s);
+    A.z[t] = s;
+}
+
+// Probe vector for the Galerkin coarse matrix: v[e][p] = phi[c][p] in every element.
+__global__ __launch_bounds__(VT) void k_probe(double *v, const double *phi, int c, int64_t nelv, int lx3)
+{
+    const int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (t >= nelv * lx3) return;
+    v[t] = phi[c * lx3 + (int)(t % lx3)];
+}
+
 // STREAM triad a = b + s c (bandwidth micro-benchmark).
 __global__ __launch_bounds__(VT) void k_triad(double *__restrict__ a, const double *__restrict__ b,
                                               const double *__restrict__ c, double s, int64_t n)
@@ -1013,6 +1178,50 @@ hipError_t sem_launch_hadamard(double *y, const double *a, const double *b, int6
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_hadamard, dim3(stream_grid(n)), dim3(VT), 0, st, y, a, b, n);
+    return hipGetLastError();
+}
+hipError_t sem_launch_corner(const CornerArgs *A, hipStream_t st)
+{
+    if (A->nelv == 0) return hipSuccess;
+    if (A->nelv > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_corner, dim3((unsigned)A->nelv), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_vgather(const VGatherArgs *A, hipStream_t st)
+{
+    if (A->nv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vgather, dim3((unsigned)((A->nv + VT - 1) / VT)), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+// iters fixed-count Jacobi-CG steps on the coarse system from x = 0 (no host sync);
+// partial must hold 2 * ceil(nv / VT) values.
+hipError_t sem_launch_coarse_cg(const CoarseArgs *A, int iters, hipStream_t st)
+{
+    if (A->nv == 0) return hipSuccess;
+    const unsigned g = (unsigned)((A->nv + VT - 1) / VT);
+    hipLaunchKernelGGL(k_ccg_start, dim3(g), dim3(VT), 0, st, *A);
+    hipLaunchKernelGGL(k_ccg_scalar, dim3(1), dim3(RT), 0, st, *A, (int64_t)g, 0);
+    for (int it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(k_ccg_spmv, dim3(g), dim3(VT), 0, st, *A);
+        hipLaunchKernelGGL(k_ccg_scalar, dim3(1), dim3(RT), 0, st, *A, (int64_t)g, 1);
+        hipLaunchKernelGGL(k_ccg_update, dim3(g), dim3(VT), 0, st, *A);
+        hipLaunchKernelGGL(k_ccg_scalar, dim3(1), dim3(RT), 0, st, *A, (int64_t)g, 2);
+        if (it + 1 < iters) hipLaunchKernelGGL(k_ccg_dir, dim3(g), dim3(VT), 0, st, *A);
+    }
+    return hipGetLastError();
+}
+hipError_t sem_launch_prolong(const ProlongArgs *A, hipStream_t st)
+{
+    const int64_t n = A->nelv * A->lx3;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prolong, dim3((unsigned)((n + VT - 1) / VT)), dim3(VT), 0, st, *A);
+    return hipGetLastError();
+}
+hipError_t sem_launch_probe(double *v, const double *phi, int c, int64_t nelv, int lx3, hipStream_t st)
+{
+    const int64_t n = nelv * lx3;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe, dim3((unsigned)((n + VT - 1) / VT)), dim3(VT), 0, st, v, phi, c, nelv, lx3);
     return hipGetLastError();
 }
 hipError_t sem_launch_dots(const DotArgs *A, unsigned grid, hipStream_t st)

@@ -38,7 +38,7 @@ class PcgParams(C.Structure):
 
 class GmresParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("precond", C.c_int),
-                ("use_x0", C.c_int)]
+                ("use_x0", C.c_int), ("coarse_iters", C.c_int)]
 
 
 class PcgInfo(C.Structure):
@@ -77,6 +77,7 @@ _SIGS = {
     "sem_stream_triad": ([_vp, _vp, _vp, C.c_double, C.c_int64, _vp], C.c_int),
     "sem_gmres_solve": ([_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(GmresParams), C.POINTER(PcgInfo), _vp],
                         C.c_int),
+    "sem_schwarz_apply": ([_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _vp], C.c_int),
     "sem_proj_create": ([_vp, _vp, _vp, _vp, C.c_int, C.POINTER(_vp)], C.c_int),
     "sem_proj_size": ([_vp, _vp, _vp, _vp], C.c_int),
     "sem_proj_reset": ([_vp], C.c_int),
@@ -346,12 +347,12 @@ def pcg_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, nfields: int = 1, 
     return out
 
 
-GMRES_PRECOND = {"jacobi": 0}
+GMRES_PRECOND = {"jacobi": 0, "schwarz": 1}
 
 
 def gmres_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, rtol: float = 1e-10, max_iter: int = 100000,
-                restart: int = 30, precond: str = "jacobi", use_x0: bool = False, stream=None,
-                raise_on_fail: bool = True):
+                restart: int = 30, precond: str = "jacobi", use_x0: bool = False, coarse_iters: int = 10,
+                stream=None, raise_on_fail: bool = True):
     """Flexible GMRES(restart) for mask QQ^T A_L x = b (the paper's pressure Krylov
     solver, Section 4).  Returns an info dict (iters = Arnoldi steps, inner_iters =
     cycles)."""
@@ -359,7 +360,8 @@ def gmres_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, rtol: float = 1e
     _dev(b, msh.n, "b")
     if x.dtype != torch.float64 or b.dtype != torch.float64:
         raise TypeError("x and b must be float64")
-    P = GmresParams(float(rtol), int(max_iter), int(restart), GMRES_PRECOND[precond], int(bool(use_x0)))
+    P = GmresParams(float(rtol), int(max_iter), int(restart), GMRES_PRECOND[precond], int(bool(use_x0)),
+                    int(coarse_iters))
     info = PcgInfo()
     st = _L.sem_gmres_solve(_ptr(x), _ptr(b), coef._h, msh._h, Xh._h, gs._h, C.byref(P), C.byref(info),
                             _stream(stream))
@@ -368,6 +370,15 @@ def gmres_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, rtol: float = 1e
     if st != SEM_OK and raise_on_fail:
         raise SemError(st, _L.sem_last_error().decode(errors="replace"))
     return d
+
+
+def schwarz_apply(z, r, coef: Coef, msh: Mesh, Xh: Space, gs: GS, coarse_iters: int = 10, stream=None):
+    """z = M0^{-1} r, the two-level additive Schwarz preconditioner (Section 4)."""
+    _dev(z, msh.n, "z")
+    _dev(r, msh.n, "r")
+    _check(_L.sem_schwarz_apply(_ptr(z), _ptr(r), coef._h, msh._h, Xh._h, gs._h, int(coarse_iters),
+                                _stream(stream)))
+    return z
 
 
 class Projection:
