@@ -186,6 +186,11 @@ def main():
             sem.ax_helm(w3, u3, P.coef, P.msh, P.Xh, 3)
         del g, u3, w3
         P.coef.set_helmholtz(1.0, 0.0)
+        # the pressure solver's kernels: ten GMRES steps with the two-level Schwarz
+        # preconditioner (local fast-diagonalisation solves, coarse CG, prolongation)
+        x.zero_()
+        sem.gmres_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-30, max_iter=10, restart=30,
+                        precond="schwarz", raise_on_fail=False)
         # projection-space kernels: fill eight vectors, then one projection with l = 8
         proj = P.projection(20)
         for k in range(9):
