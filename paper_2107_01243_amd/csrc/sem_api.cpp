@@ -44,6 +44,7 @@ using namespace sem;
     extern "C" hipError_t sem_launch_cg1_f64_lx##L(const CgMatvecArgs<double> *, const double *, int,       \
                                                    hipStream_t);                                            \
     extern "C" hipError_t sem_launch_fdm_lx##L(const FdmArgs *, hipStream_t);                               \
+    extern "C" hipError_t sem_launch_prolong_lx##L(const ProlongArgs *, hipStream_t);                       \
     extern "C" hipError_t sem_launch_adj_f64_lx##L(const AdjArgs<double> *, const double *, hipStream_t);   \
     extern "C" hipError_t sem_launch_adj_f32_lx##L(const AdjArgs<float> *, const double *, hipStream_t);    \
     extern "C" hipError_t sem_launch_geom_lx##L(const GeomArgs *, const double *, const double *,           \
@@ -82,10 +83,11 @@ hipError_t sem_launch_dots_finish(const double *, int64_t, int, double *, hipStr
 hipError_t sem_launch_mdot(const MdotArgs *, unsigned, hipStream_t);
 hipError_t sem_launch_comb(const CombArgs *, hipStream_t);
 hipError_t sem_launch_hadamard(double *, const double *, const double *, int64_t, hipStream_t);
+unsigned sem_arn_grid(int64_t n);
+hipError_t sem_launch_arn(const ArnArgs *, int, hipStream_t);
+hipError_t sem_launch_arn_finish(const double *, int64_t, int, int, double *, hipStream_t);
 hipError_t sem_launch_corner(const CornerArgs *, hipStream_t);
-hipError_t sem_launch_vgather(const VGatherArgs *, hipStream_t);
 hipError_t sem_launch_coarse_cg(const CoarseArgs *, int, hipStream_t);
-hipError_t sem_launch_prolong(const ProlongArgs *, hipStream_t);
 hipError_t sem_launch_probe(double *, const double *, int, int64_t, int, hipStream_t);
 hipError_t sem_launch_residual(double *, const double *, const double *, const double *, int64_t, int,
                                hipStream_t);
@@ -107,6 +109,7 @@ struct LxFns {
     hipError_t (*cg32)(const CgMatvecArgs<float> *, const double *, int, hipStream_t);
     hipError_t (*cg1)(const CgMatvecArgs<double> *, const double *, int, hipStream_t);
     hipError_t (*fdm)(const FdmArgs *, hipStream_t);
+    hipError_t (*prolong)(const ProlongArgs *, hipStream_t);
     hipError_t (*adj64)(const AdjArgs<double> *, const double *, hipStream_t);
     hipError_t (*adj32)(const AdjArgs<float> *, const double *, hipStream_t);
     hipError_t (*geom)(const GeomArgs *, const double *, const double *, hipStream_t);
@@ -119,7 +122,7 @@ const LxFns &fns(int lx)
 {
 #define SEM_ROW(L)                                                                                 \
     {sem_launch_ax_f64_lx##L, sem_launch_ax_f32_lx##L, sem_launch_cg_f64_lx##L, sem_launch_cg_f32_lx##L, \
-     sem_launch_cg1_f64_lx##L, sem_launch_fdm_lx##L,                                               \
+     sem_launch_cg1_f64_lx##L, sem_launch_fdm_lx##L, sem_launch_prolong_lx##L,                     \
      sem_launch_adj_f64_lx##L, sem_launch_adj_f32_lx##L, sem_launch_geom_lx##L, sem_launch_diag_lx##L,  \
      sem_cg_nblocks_f64_lx##L, sem_cg_nblocks_f32_lx##L},
     static const LxFns table[] = {SEM_LX_LIST(SEM_ROW)};
@@ -288,25 +291,26 @@ struct SchwarzData {
     bool valid = false;
     const void *gs = nullptr;
     double *S = nullptr, *lam = nullptr;  // [nelv][3][lx][lx], [nelv][3][lx]
-    double *phi = nullptr;                // [8][lx^3]
+    double *phi = nullptr;                // [8][lx^3] (setup probes)
+    double *lin = nullptr;                // [2][lx] linear functions at the GLL points
     int32_t *cvert = nullptr;             // [nelv][8]
     int64_t nv = 0;
     int64_t *v_ptr = nullptr;
     int32_t *v_idx = nullptr;
     uint8_t *v_dir = nullptr;
-    int64_t *rp = nullptr;
-    int32_t *ci = nullptr;
-    double *val = nullptr, *dinv0 = nullptr;
+    int width = 0;                        // ELL row width of the coarse matrix
+    int32_t *ell_ci = nullptr;            // [width][nv]
+    double *ell_val = nullptr, *dinv0 = nullptr;
     double *part = nullptr;               // [nelv * 8]
-    double *cv = nullptr;                 // [6][nv]: b0, x, r, z, p, q
-    double *cpart = nullptr;              // [2][ceil(nv / 256)]
-    double *cscal = nullptr;              // [4]
+    double *cv = nullptr;                 // [6][nv]: x, r, z, p0, p1, q
+    double *cpart = nullptr;              // [3][ceil(nv / 256)]
     uint8_t *mult = nullptr;              // [n]
     void release()
     {
-        dfree(S); dfree(lam); dfree(phi); dfree(cvert); dfree(v_ptr); dfree(v_idx); dfree(v_dir);
-        dfree(rp); dfree(ci); dfree(val); dfree(dinv0); dfree(part); dfree(cv); dfree(cpart); dfree(cscal);
+        dfree(S); dfree(lam); dfree(phi); dfree(lin); dfree(cvert); dfree(v_ptr); dfree(v_idx); dfree(v_dir);
+        dfree(ell_ci); dfree(ell_val); dfree(dinv0); dfree(part); dfree(cv); dfree(cpart);
         dfree(mult);
+        width = 0;
         valid = false;
         gs = nullptr;
         nv = 0;
@@ -1881,6 +1885,11 @@ static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
                         for (int i = 0; i < lx; ++i)
                             phi[(size_t)c8 * lx3 + i + lx * (j + lx * k)] = l1(aa, i) * l1(bb, j) * l1(cc, k);
             }
+    std::vector<double> lin((size_t)2 * lx);
+    for (int i = 0; i < lx; ++i) {
+        lin[i] = (1.0 - Xh->xi[i]) / 2.0;
+        lin[lx + i] = (1.0 + Xh->xi[i]) / 2.0;
+    }
     // coarse vertices: the global ids of the element corners
     const sem_mesh msh = c->msh;
     std::vector<int64_t> cg((size_t)E * 8);
@@ -1914,6 +1923,7 @@ static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
     SEM_TRY(dalloc(&Z.S, S.size()));
     SEM_TRY(dalloc(&Z.lam, lam.size()));
     SEM_TRY(dalloc(&Z.phi, phi.size()));
+    SEM_TRY(dalloc(&Z.lin, lin.size()));
     SEM_TRY(dalloc(&Z.cvert, cvert.size()));
     SEM_TRY(dalloc(&Z.v_ptr, vptr.size()));
     SEM_TRY(dalloc(&Z.v_idx, vidx.size()));
@@ -1923,6 +1933,7 @@ static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
     HIP_TRY(hipMemcpy(Z.S, S.data(), S.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(Z.lam, lam.data(), lam.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(Z.phi, phi.data(), phi.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(Z.lin, lin.data(), lin.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(Z.cvert, cvert.data(), cvert.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(Z.v_ptr, vptr.data(), vptr.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(Z.v_idx, vidx.data(), vidx.size() * 4, hipMemcpyHostToDevice));
@@ -1974,19 +1985,28 @@ static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
     }
     for (int64_t v = 0; v < nv; ++v) rp[v + 1] += rp[v];
     for (double &d : dg) d = (d != 0.0) ? 1.0 / d : 0.0;
-    SEM_TRY(dalloc(&Z.rp, rp.size()));
-    SEM_TRY(dalloc(&Z.ci, std::max<size_t>(ci.size(), 1)));
-    SEM_TRY(dalloc(&Z.val, std::max<size_t>(val.size(), 1)));
+    // ELL form, column-major: entry w of row v at w * nv + v; short rows padded with
+    // value 0 and the row's own column
+    int width = 1;
+    for (int64_t v = 0; v < nv; ++v) width = std::max(width, (int)(rp[v + 1] - rp[v]));
+    std::vector<int32_t> eci((size_t)width * nv);
+    std::vector<double> evl((size_t)width * nv, 0.0);
+    for (int64_t v = 0; v < nv; ++v)
+        for (int w = 0; w < width; ++w) {
+            const int64_t q = rp[v] + w;
+            const bool in = q < rp[v + 1];
+            eci[(size_t)w * nv + v] = in ? ci[q] : (int32_t)v;
+            evl[(size_t)w * nv + v] = in ? val[q] : 0.0;
+        }
+    SEM_TRY(dalloc(&Z.ell_ci, eci.size()));
+    SEM_TRY(dalloc(&Z.ell_val, evl.size()));
     SEM_TRY(dalloc(&Z.dinv0, (size_t)nv));
     SEM_TRY(dalloc(&Z.cv, (size_t)6 * nv));
-    SEM_TRY(dalloc(&Z.cpart, (size_t)2 * ((nv + 255) / 256)));
-    SEM_TRY(dalloc(&Z.cscal, 4));
-    HIP_TRY(hipMemcpy(Z.rp, rp.data(), rp.size() * 8, hipMemcpyHostToDevice));
-    if (!ci.empty()) {
-        HIP_TRY(hipMemcpy(Z.ci, ci.data(), ci.size() * 4, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(Z.val, val.data(), val.size() * 8, hipMemcpyHostToDevice));
-    }
+    SEM_TRY(dalloc(&Z.cpart, (size_t)3 * ((nv + 255) / 256)));
+    HIP_TRY(hipMemcpy(Z.ell_ci, eci.data(), eci.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(Z.ell_val, evl.data(), evl.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(Z.dinv0, dg.data(), dg.size() * 8, hipMemcpyHostToDevice));
+    Z.width = width;
     Z.nv = nv;
     Z.gs = g;
     Z.valid = true;
@@ -1998,21 +2018,17 @@ static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
 static sem_status schwarz_apply(sem_coef c, sem_gs g, double *z, const double *r, int coarse_iters, hipStream_t st)
 {
     SchwarzData &Z = c->sz;
-    const int lx = c->lx, lx3 = lx * lx * lx;
-    const FdmArgs F{z, r, Z.S, Z.lam, c->h1s, c->h2s, c->nelv};
+    const int lx = c->lx;
+    const FdmArgs F{z, r, Z.S, Z.lam, g->d_owner, Z.lin, Z.part, c->h1s, c->h2s, c->nelv};
     HIP_TRY(fns(lx).fdm(&F, st));
     SEM_TRY(launch_gs<double>(z, 1, g, nullptr, nullptr, st));
-    const CornerArgs CA{r, g->d_owner, Z.phi, Z.part, c->nelv, lx3};
-    HIP_TRY(sem_launch_corner(&CA, st));
     const int64_t nv = Z.nv;
-    double *b0 = Z.cv, *x0 = Z.cv + nv;
-    const VGatherArgs VA{b0, Z.part, Z.v_ptr, Z.v_idx, Z.v_dir, nv};
-    HIP_TRY(sem_launch_vgather(&VA, st));
-    const CoarseArgs CC{Z.rp, Z.ci, Z.val, Z.dinv0, b0, x0, Z.cv + 2 * nv, Z.cv + 3 * nv, Z.cv + 4 * nv,
-                        Z.cv + 5 * nv, Z.cpart, Z.cscal, nv};
+    double *x0 = Z.cv;
+    const CoarseArgs CC{Z.ell_ci, Z.ell_val, Z.width, Z.dinv0, Z.part, Z.v_ptr, Z.v_idx, Z.v_dir,
+                        x0, Z.cv + nv, Z.cv + 2 * nv, Z.cv + 3 * nv, Z.cv + 4 * nv, Z.cv + 5 * nv, Z.cpart, nv};
     HIP_TRY(sem_launch_coarse_cg(&CC, coarse_iters, st));
-    const ProlongArgs PA{z, Z.mult, Z.phi, x0, Z.cvert, c->nelv, lx3};
-    HIP_TRY(sem_launch_prolong(&PA, st));
+    const ProlongArgs PA{z, Z.mult, Z.lin, x0, Z.cvert, c->nelv};
+    HIP_TRY(fns(lx).prolong(&PA, st));
     HIP_TRY(sem_launch_mask(z, 0, c->msh->d_dir_idx, (int64_t)c->msh->dir_idx.size(), c->n, 1, st));
     return SEM_OK;
 }
@@ -2052,6 +2068,33 @@ static sem_status gmres_precond(sem_coef c, sem_gs g, const sem_gmres_params *P,
     return SEM_OK;
 }
 
+// One Arnoldi orthogonalisation of w against V_0..V_{m-1} (m <= ARN_MAXV) by classical
+// Gram-Schmidt run twice, in three passes over the data and one host sync:
+//   h = V^T w (and |w|^2);  w' = w - V h, h2 = V^T w', |w'|^2;
+//   w'' = (w' - V h2) / |w''|, with |w''|^2 = |w'|^2 - |h2|^2.
+// out holds two result rows of stride ostride (>= m + 3) on the device; on return
+// h[i] = h_i + h2_i and *hn = |w''| (0 when w lies in the span: w'' is then 0).
+static sem_status arnoldi_step(const VecCtx &X, const double *V, int64_t n, int m, double *w, double *out,
+                               int ostride, double *h, double *hn, hipStream_t st)
+{
+    const int64_t G = sem_arn_grid(n);
+    double *o1 = out, *o2 = out + ostride;
+    ArnArgs A{V, n, m, w, w, X.owner, nullptr, nullptr, X.partial, n};
+    HIP_TRY(sem_launch_arn(&A, 0, st));
+    HIP_TRY(sem_launch_arn_finish(X.partial, G, m + 1, 0, o1, st));
+    A.coef = o1;
+    HIP_TRY(sem_launch_arn(&A, 1, st));
+    HIP_TRY(sem_launch_arn_finish(X.partial, G, m + 1, 1, o2, st));
+    A.coef = o2;
+    A.scale = o2 + m + 2;
+    HIP_TRY(sem_launch_arn(&A, 2, st));
+    HIP_TRY(hipMemcpyAsync(X.h_out, out, sizeof(double) * (ostride + m + 3), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < m; ++i) h[i] = X.h_out[i] + X.h_out[ostride + i];
+    *hn = X.h_out[ostride + m + 1];
+    return SEM_OK;
+}
+
 static sem_status gmres_run(double *x, const double *b, sem_coef c, sem_gs g, const sem_gmres_params *P,
                             sem_pcg_info *info, hipStream_t st)
 {
@@ -2064,9 +2107,9 @@ static sem_status gmres_run(double *x, const double *b, sem_coef c, sem_gs g, co
         W.gm_hout = nullptr;
         W.gm_m = 0;
         SEM_TRY(dalloc(&W.gm, (size_t)(2 * m + 2) * n));
-        SEM_TRY(dalloc(&W.gm_part, (size_t)PB * sem_vec_grid(n)));
-        SEM_TRY(dalloc(&W.gm_out, (size_t)m + 2));
-        HIP_TRY(hipHostMalloc((void **)&W.gm_hout, sizeof(double) * (m + 2), hipHostMallocDefault));
+        SEM_TRY(dalloc(&W.gm_part, std::max((size_t)PB * sem_vec_grid(n), (size_t)(ARN_MAXV + 1) * sem_arn_grid(n))));
+        SEM_TRY(dalloc(&W.gm_out, (size_t)2 * (m + 3)));
+        HIP_TRY(hipHostMalloc((void **)&W.gm_hout, sizeof(double) * 2 * (m + 3), hipHostMallocDefault));
         W.gm_m = m;
     }
     double *V = W.gm;                          // V_0 .. V_m
@@ -2101,19 +2144,28 @@ static sem_status gmres_run(double *x, const double *b, sem_coef c, sem_gs g, co
             double *Vj = V + (int64_t)j * n, *Vn = V + (int64_t)(j + 1) * n, *Zj = Z + (int64_t)j * n;
             SEM_TRY(gmres_precond(c, g, P, Zj, Vj, st));
             SEM_TRY(gmres_apply(c, g, Vn, Zj, st));
-            // classical Gram-Schmidt against V_0..V_j, twice
-            SEM_TRY(vdots(X, V, n, j + 1, Vn, h.data(), st));
-            for (int i = 0; i <= j; ++i) h2[i] = -h[i];
-            SEM_TRY(vcomb(X, Vn, nullptr, V, n, j + 1, h2.data(), 1, st));
-            SEM_TRY(vdots(X, V, n, j + 1, Vn, h2.data(), st));
-            for (int i = 0; i <= j; ++i) {
-                h[i] += h2[i];
-                h2[i] = -h2[i];
+            // classical Gram-Schmidt against V_0..V_j, twice; V_{j+1} normalised
+            double hn;
+            if (j + 1 <= ARN_MAXV) {
+                SEM_TRY(arnoldi_step(X, V, n, j + 1, Vn, W.gm_out, m + 3, h.data(), &hn, st));
+            } else {
+                SEM_TRY(vdots(X, V, n, j + 1, Vn, h.data(), st));
+                for (int i = 0; i <= j; ++i) h2[i] = -h[i];
+                SEM_TRY(vcomb(X, Vn, nullptr, V, n, j + 1, h2.data(), 1, st));
+                SEM_TRY(vdots(X, V, n, j + 1, Vn, h2.data(), st));
+                for (int i = 0; i <= j; ++i) {
+                    h[i] += h2[i];
+                    h2[i] = -h2[i];
+                }
+                SEM_TRY(vcomb(X, Vn, nullptr, V, n, j + 1, h2.data(), 1, st));
+                double hh;
+                SEM_TRY(vdots(X, Vn, n, 1, Vn, &hh, st));
+                hn = std::sqrt(hh);
+                if (hn > 1e-300) {
+                    const double ih = 1.0 / hn;
+                    SEM_TRY(vcomb(X, Vn, nullptr, Vn, n, 1, &ih, 0, st));
+                }
             }
-            SEM_TRY(vcomb(X, Vn, nullptr, V, n, j + 1, h2.data(), 1, st));
-            double hh;
-            SEM_TRY(vdots(X, Vn, n, 1, Vn, &hh, st));
-            double hn = std::sqrt(hh);
             total += 1;
             jj = j + 1;
             // rotate column j with the earlier Givens rotations, then annihilate H[j+1][j]
@@ -2131,8 +2183,6 @@ static sem_status gmres_run(double *x, const double *b, sem_coef c, sem_gs g, co
             gv[j] = cs[j] * gv[j];
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
             if (std::fabs(gv[j + 1]) <= P->rtol * bn || hn <= 1e-300) break;  // converged or invariant space
-            const double ih = 1.0 / hn;
-            SEM_TRY(vcomb(X, Vn, nullptr, Vn, n, 1, &ih, 0, st));
         }
         if (jj == 0) break;
         // y = R^{-1} g (upper triangular), x += Z y

@@ -117,13 +117,30 @@ struct DiagArgs {
 // Local solves of the two-level Schwarz preconditioner (fast diagonalisation):
 // z_e = (S_t x S_s x S_r) diag(1 / (h1 (lr_i + ls_j + lt_k) + h2)) (S_t x S_s x S_r)^T r_e,
 // with per element and direction the eigenvectors S (row-major [point][mode]) and
-// eigenvalues of the 1-D generalised problem K S = M S Lambda.
+// eigenvalues of the 1-D generalised problem K S = M S Lambda.  When part is set,
+// the same pass also forms the coarse restriction of r: per element the eight sums
+// over its owned points of r times the trilinear corner functions.
 struct FdmArgs {
-    double *z;          // [nelv][lx^3]
-    const double *r;    // [nelv][lx^3]
-    const double *S;    // [nelv][3][lx][lx]
-    const double *lam;  // [nelv][3][lx]
+    double *z;             // [nelv][lx^3]
+    const double *r;       // [nelv][lx^3]
+    const double *S;       // [nelv][3][lx][lx]
+    const double *lam;     // [nelv][3][lx]
+    const uint8_t *owner;  // [nelv][lx^3] one copy per global id (restriction weights)
+    const double *lin;     // [2][lx]: (1 - xi_i) / 2, (1 + xi_i) / 2 at the GLL points
+    double *part;          // [nelv][8] restriction sums (corner c = a + 2 b + 4 c'), or nullptr
     double h1, h2;
+    int64_t nelv;
+};
+
+// Coarse prolongation with the multiplicity average of the local solves:
+// z = z / mult + sum over the eight corners c of e0[cvert[e][c]] phi_c, phi_c the
+// trilinear corner function (a product of the linear functions in lin).
+struct ProlongArgs {
+    double *z;
+    const uint8_t *mult;
+    const double *lin;     // [2][lx]
+    const double *e0;      // coarse vector
+    const int32_t *cvert;  // [nelv][8]
     int64_t nelv;
 };
 

@@ -156,6 +156,27 @@ struct CombArgs {
     int64_t n;
 };
 
+// ---------------------------------------------------------------- GMRES Arnoldi
+// One pass over the data against up to ARN_MAXV basis vectors (unique-node product):
+//   mode 0: partial dots (V_i, w), i < m, and (w, w);
+//   mode 1: y = w - sum_i coef[i] V_i, partial dots (V_i, y) and (y, y);
+//   mode 2: y = (w - sum_i coef[i] V_i) * scale[0].
+// Partials are [m + 1][grid] (the squared norm last); coef and scale are device values
+// (outputs of the previous reduction), so a whole Gram-Schmidt step needs no host sync.
+constexpr int ARN_MAXV = 32;
+struct ArnArgs {
+    const double *V;       // basis vector i at V + i * ld
+    int64_t ld;
+    int m;                 // basis vectors in use, 1..ARN_MAXV
+    const double *w;       // input
+    double *y;             // output (modes 1, 2); may be w
+    const uint8_t *owner;  // one copy per global id
+    const double *coef;    // [m] (modes 1, 2)
+    const double *scale;   // [1] (mode 2)
+    double *partial;       // [m + 1][grid] (modes 0, 1)
+    int64_t n;
+};
+
 // ---------------------------------------------------------------- two-level Schwarz
 // out[e][c] = sum over element e's points p of phi[c][p] v[e][p] (owner[p] if owner).
 struct CornerArgs {
@@ -167,38 +188,23 @@ struct CornerArgs {
     int lx3;
 };
 
-// Coarse vector from the corner sums: b0[v] = sum over (e, c) at vertex v, ascending e.
-struct VGatherArgs {
-    double *b0;
-    const double *part;    // [nelv * 8]
-    const int64_t *ptr;    // [nv + 1]
-    const int32_t *idx;    // e * 8 + c
-    const uint8_t *dir;    // [nv] Dirichlet vertex (b0 = 0)
-    int64_t nv;
-};
-
-// Fixed-count Jacobi-CG on the coarse CSR matrix (Dirichlet vertices: identity rows).
+// Fixed-count Jacobi-CG on the coarse system (Dirichlet vertices: identity rows), the
+// matrix in ELL form (column-major [width][nv]; a row's entries in ascending column,
+// padding value 0 with the row's own column).  The right-hand side is gathered from
+// the per-element restriction sums: b[v] = sum over (e, c) at vertex v, ascending e
+// (0 at Dirichlet vertices).
 struct CoarseArgs {
-    const int64_t *rp;
     const int32_t *ci;
     const double *val;
+    int width;
     const double *dinv;
-    const double *b;
-    double *x, *r, *z, *p, *q;
-    double *partial;       // [2][grid]
-    double *scal;          // [4]: rz, pq, alpha, beta
+    const double *part;    // [nelv * 8] restriction sums
+    const int64_t *vptr;   // [nv + 1]
+    const int32_t *vidx;   // e * 8 + c
+    const uint8_t *vdir;   // [nv]
+    double *x, *r, *z, *p0, *p1, *q;
+    double *partial;       // [3][grid]: (r, z) in two slots, (p, q)
     int64_t nv;
-};
-
-// z = z / mult + sum_c phi[c][p] e0[cvert[e][c]]
-struct ProlongArgs {
-    double *z;
-    const uint8_t *mult;
-    const double *phi;
-    const double *e0;
-    const int32_t *cvert;  // [nelv][8]
-    int64_t nelv;
-    int lx3;
 };
 
 }  // namespace sem

@@ -308,6 +308,101 @@ __global__ __launch_bounds__(VT) void k_comb(CombArgs A)
     }
 }
 
+// Arnoldi pass (see ArnArgs).  Each workgroup streams one contiguous chunk of
+// points; every lane keeps the m basis values of its point in registers, so the
+// combination and the dots of the combined vector need one read of each vector.
+template <int MV, int MODE>
+__global__ __launch_bounds__(VT) void k_arn(ArnArgs A, int64_t chunk)
+{
+    const int m = A.m;
+    double c[MV];
+    double sc = 1.0;
+    if constexpr (MODE != 0) {
+#pragma unroll
+        for (int i = 0; i < MV; ++i) c[i] = (i < m) ? A.coef[i] : 0.0;
+        if constexpr (MODE == 2) sc = A.scale[0];
+    }
+    double acc[MV + 1];
+#pragma unroll
+    for (int i = 0; i <= MV; ++i) acc[i] = 0.0;
+    const int64_t t0 = (int64_t)blockIdx.x * chunk;
+    const int64_t t1 = min(A.n, t0 + chunk);
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += VT) {
+        double v[MV];
+#pragma unroll
+        for (int i = 0; i < MV; ++i) v[i] = (i < m) ? A.V[i * A.ld + t] : 0.0;
+        double y = A.w[t];
+        if constexpr (MODE != 0) {
+#pragma unroll
+            for (int i = 0; i < MV; ++i)
+                if (i < m) y = fma(-c[i], v[i], y);
+            if constexpr (MODE == 2) y *= sc;
+            A.y[t] = y;
+        }
+        if constexpr (MODE != 2) {
+            const double yo = A.owner[t] ? y : 0.0;
+#pragma unroll
+            for (int i = 0; i < MV; ++i)
+                if (i < m) acc[i] = fma(v[i], yo, acc[i]);
+            acc[MV] = fma(y, yo, acc[MV]);
+        }
+    }
+    if constexpr (MODE != 2) {
+        __shared__ double sh[VT / 64][MV + 1];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int i = 0; i <= MV; ++i) {
+            if (i < m || i == MV) {
+                double x = acc[i];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+                if (lane == 0) sh[wave][i] = x;
+            }
+        }
+        __syncthreads();
+        const int q = threadIdx.x;
+        if (q <= m) {
+            const int src = (q < m) ? q : MV;
+            double x = 0.0;
+#pragma unroll
+            for (int w4 = 0; w4 < VT / 64; ++w4) x += sh[w4][src];
+            A.partial[(int64_t)q * gridDim.x + blockIdx.x] = x;
+        }
+    }
+}
+
+// Sums of nq rows of per-workgroup partials, one wave per row, fixed order.  With
+// pyth, the last row is a squared norm |y|^2 and the others the coefficients h of a
+// second Gram-Schmidt pass: out[nq] = sqrt(|y|^2 - |h|^2) (the norm after that pass,
+// by the Pythagorean identity) and out[nq + 1] = its reciprocal (0 if not positive).
+__global__ __launch_bounds__(RT) void k_arn_finish(const double *partial, int64_t nblk, int nq, int pyth,
+                                                   double *out)
+{
+    __shared__ double sh[ARN_MAXV + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = wave; q < nq; q += RT / 64) {
+        double s = 0.0;
+        for (int64_t b = lane; b < nblk; b += 64) s += partial[(int64_t)q * nblk + b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) {
+            out[q] = s;
+            sh[q] = s;
+        }
+    }
+    if (pyth) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int m = nq - 1;
+            double hh = sh[m];
+            for (int i = 0; i < m; ++i) hh = fma(-sh[i], sh[i], hh);
+            hh = hh > 0.0 ? hh : 0.0;
+            out[nq] = sqrt(hh);
+            out[nq + 1] = hh > 0.0 ? 1.0 / sqrt(hh) : 0.0;
+        }
+    }
+}
+
 // y = a * b pointwise (point-Jacobi preconditioning of a Krylov vector).
 __global__ __launch_bounds__(VT) void k_hadamard(double *y, const double *a, const double *b, int64_t n)
 {
@@ -348,128 +443,114 @@ __global__ __launch_bounds__(VT) void k_corner(CornerArgs A)
     }
 }
 
-__global__ __launch_bounds__(VT) void k_vgather(VGatherArgs A)
+// Sum of the nblk per-workgroup partials in one fixed order, returned to every lane
+// of the workgroup.  Each workgroup of a launch computes the same value, so a
+// kernel can use a grid-wide reduction of the previous launch without a separate
+// scalar kernel (the coarse system has only a few hundred partials).
+__device__ __forceinline__ double all_sum(const double *part, int64_t nblk, double *sh)
 {
-    const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
-    if (v >= A.nv) return;
-    double s = 0.0;
-    if (!A.dir[v])
-        for (int64_t q = A.ptr[v]; q < A.ptr[v + 1]; ++q) s += A.part[A.idx[q]];
-    A.b0[v] = s;
+    if (threadIdx.x < 64) {
+        double s = 0.0;
+        for (int64_t q = threadIdx.x; q < nblk; q += 64) s += part[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (threadIdx.x == 0) sh[0] = s;
+    }
+    __syncthreads();
+    const double v = sh[0];
+    __syncthreads();
+    return v;
 }
 
-// Coarse Jacobi-CG: start (x = 0, r = b, z = D r, p = z, partial of r.z).
+__device__ __forceinline__ void block_partial(double v, double *out, double *sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < VT / 64; ++q) s += sh[q];
+        *out = s;
+    }
+}
+
+// Coarse Jacobi-CG, start: b gathered from the restriction sums; x = 0, r = b,
+// z = D r; partial of (r, z) into slot 0.
 __global__ __launch_bounds__(VT) void k_ccg_start(CoarseArgs A)
 {
     __shared__ double sh[VT / 64];
     const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
     double rz = 0.0;
     if (v < A.nv) {
-        const double rv = A.b[v], zv = A.dinv[v] * rv;
+        double b = 0.0;
+        if (!A.vdir[v])
+            for (int64_t q = A.vptr[v]; q < A.vptr[v + 1]; ++q) b += A.part[A.vidx[q]];
+        const double zv = A.dinv[v] * b;
         A.x[v] = 0.0;
-        A.r[v] = rv;
+        A.r[v] = b;
         A.z[v] = zv;
-        A.p[v] = zv;
-        rz = rv * zv;
+        rz = b * zv;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) rz += __shfl_xor(rz, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = rz;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < VT / 64; ++q) s += sh[q];
-        A.partial[blockIdx.x] = s;
-    }
+    block_partial(rz, A.partial + blockIdx.x, sh);
 }
 
-// q = A p, partial of p.q
-__global__ __launch_bounds__(VT) void k_ccg_spmv(CoarseArgs A)
+// Step it, first half: beta from the two latest (r, z) sums (it > 0), the new
+// direction p = z + beta p_old formed for the own row and, on the fly, for every
+// column the row touches; q = A p; partial of (p, q) into slot 2.  p alternates
+// between p0 (even steps) and p1 (odd steps).
+__global__ __launch_bounds__(VT) void k_ccg_spmv(CoarseArgs A, int it)
 {
     __shared__ double sh[VT / 64];
+    const int64_t g = gridDim.x;
+    double beta = 0.0;
+    if (it > 0) {
+        const double rz = all_sum(A.partial + (it & 1) * g, g, sh);
+        const double rz_old = all_sum(A.partial + ((it + 1) & 1) * g, g, sh);
+        beta = (rz_old != 0.0) ? rz / rz_old : 0.0;
+    }
+    double *pn = (it & 1) ? A.p1 : A.p0;
+    const double *po = (it & 1) ? A.p0 : A.p1;
     const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
     double pq = 0.0;
     if (v < A.nv) {
         double s = 0.0;
-        for (int64_t k = A.rp[v]; k < A.rp[v + 1]; ++k) s = fma(A.val[k], A.p[A.ci[k]], s);
-        A.q[v] = s;
-        pq = A.p[v] * s;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) pq += __shfl_xor(pq, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = pq;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < VT / 64; ++q) s += sh[q];
-        A.partial[gridDim.x + blockIdx.x] = s;
-    }
-}
-
-// Single workgroup: which = 0 sets rz from partial[0..nblk) (start); 1 sets alpha =
-// rz / pq from partial[nblk..2nblk); 2 sets beta = rz_new / rz, rz = rz_new.
-__global__ __launch_bounds__(RT) void k_ccg_scalar(CoarseArgs A, int64_t nblk, int which)
-{
-    __shared__ double sh[RT];
-    const double s = block_sum_fixed<RT>(A.partial + (which == 1 ? nblk : 0), nblk, sh);
-    if (threadIdx.x == 0) {
-        if (which == 0) {
-            A.scal[0] = s;
-        } else if (which == 1) {
-            A.scal[2] = (s > 0.0 && isfinite(s)) ? A.scal[0] / s : 0.0;
-        } else {
-            A.scal[3] = (A.scal[0] != 0.0) ? s / A.scal[0] : 0.0;
-            A.scal[0] = s;
+        for (int w = 0; w < A.width; ++w) {
+            const int64_t k = (int64_t)w * A.nv + v;
+            const int32_t c = A.ci[k];
+            const double pc = (it > 0) ? fma(beta, po[c], A.z[c]) : A.z[c];
+            s = fma(A.val[k], pc, s);
         }
+        const double pv = (it > 0) ? fma(beta, po[v], A.z[v]) : A.z[v];
+        pn[v] = pv;
+        A.q[v] = s;
+        pq = pv * s;
     }
+    block_partial(pq, A.partial + 2 * g + blockIdx.x, sh);
 }
 
-// x += alpha p; r -= alpha q; z = D r; partial of r.z
-__global__ __launch_bounds__(VT) void k_ccg_update(CoarseArgs A)
+// Step it, second half: alpha = (r, z) / (p, q); x += alpha p, r -= alpha q,
+// z = D r; partial of the new (r, z) into the other slot.
+__global__ __launch_bounds__(VT) void k_ccg_update(CoarseArgs A, int it)
 {
     __shared__ double sh[VT / 64];
+    const int64_t g = gridDim.x;
+    const double rz = all_sum(A.partial + (it & 1) * g, g, sh);
+    const double pq = all_sum(A.partial + 2 * g, g, sh);
+    const double alpha = (pq > 0.0 && isfinite(pq)) ? rz / pq : 0.0;
+    const double *pn = (it & 1) ? A.p1 : A.p0;
     const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
-    const double alpha = A.scal[2];
-    double rz = 0.0;
+    double rzn = 0.0;
     if (v < A.nv) {
-        A.x[v] = fma(alpha, A.p[v], A.x[v]);
+        A.x[v] = fma(alpha, pn[v], A.x[v]);
         const double rv = fma(-alpha, A.q[v], A.r[v]);
         A.r[v] = rv;
         const double zv = A.dinv[v] * rv;
         A.z[v] = zv;
-        rz = rv * zv;
+        rzn = rv * zv;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) rz += __shfl_xor(rz, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = rz;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < VT / 64; ++q) s += sh[q];
-        A.partial[blockIdx.x] = s;
-    }
-}
-
-// p = z + beta p
-__global__ __launch_bounds__(VT) void k_ccg_dir(CoarseArgs A)
-{
-    const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
-    if (v < A.nv) A.p[v] = fma(A.scal[3], A.p[v], A.z[v]);
-}
-
-__global__ __launch_bounds__(VT) void k_prolong(ProlongArgs A)
-{
-    const int64_t t = (int64_t)blockIdx.x * VT + threadIdx.x;
-    if (t >= A.nelv * A.lx3) return;
-    const int64_t e = t / A.lx3;
-    const int p = (int)(t - e * A.lx3);
-    double s = A.z[t] / (double)A.mult[t];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) s = fma(A.phi[c * A.lx3 + p], A.e0[A.cvert[e * 8 + c]], s);
-    A.z[t] = s;
+    block_partial(rzn, A.partial + ((it + 1) & 1) * g + blockIdx.x, sh);
 }
 
 // Probe vector for the Galerkin coarse matrix: v[e][p] = phi[c][p] in every element.
@@ -1050,6 +1131,29 @@ static hipError_t launch_gs_t(const GsArgs<T> *A, hipStream_t st)
     hipLaunchKernelGGL(k_gs<T>, dim3(gs_grid(A->npairs + A->nblocks)), dim3(VT), 0, st, *A);
     return hipGetLastError();
 }
+// Workgroups of the Arnoldi passes: contiguous chunks of whole 256-point rows, at
+// most 2048 workgroups (a few per CU), so the partial rows stay short.
+static int64_t arn_chunk(int64_t n)
+{
+    const int64_t rows = (n + VT - 1) / VT;
+    const int64_t per = (rows + 2047) / 2048;
+    return (per < 1 ? 1 : per) * VT;
+}
+static unsigned arn_grid(int64_t n)
+{
+    const int64_t c = arn_chunk(n);
+    const int64_t g = (n + c - 1) / c;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+template <int MV>
+static void launch_arn(const ArnArgs &A, int mode, hipStream_t st)
+{
+    const unsigned g = arn_grid(A.n);
+    const int64_t c = arn_chunk(A.n);
+    if (mode == 0) hipLaunchKernelGGL((k_arn<MV, 0>), dim3(g), dim3(VT), 0, st, A, c);
+    else if (mode == 1) hipLaunchKernelGGL((k_arn<MV, 1>), dim3(g), dim3(VT), 0, st, A, c);
+    else hipLaunchKernelGGL((k_arn<MV, 2>), dim3(g), dim3(VT), 0, st, A, c);
+}
 extern "C" {
 hipError_t sem_launch_gs_f64(const GsArgs<double> *A, hipStream_t st) { return launch_gs_t<double>(A, st); }
 hipError_t sem_launch_gs_f32(const GsArgs<float> *A, hipStream_t st) { return launch_gs_t<float>(A, st); }
@@ -1174,6 +1278,23 @@ hipError_t sem_launch_comb(const CombArgs *A, hipStream_t st)
     hipLaunchKernelGGL(k_comb, dim3(stream_grid(A->n)), dim3(VT), 0, st, *A);
     return hipGetLastError();
 }
+unsigned sem_arn_grid(int64_t n) { return arn_grid(n); }
+hipError_t sem_launch_arn(const ArnArgs *A, int mode, hipStream_t st)
+{
+    if (A->m < 1 || A->m > ARN_MAXV || mode < 0 || mode > 2 || A->n < 1) return hipErrorInvalidValue;
+    if (mode != 0 && !A->coef) return hipErrorInvalidValue;
+    if (mode == 2 && !A->scale) return hipErrorInvalidValue;
+    if (A->m <= 8) launch_arn<8>(*A, mode, st);
+    else if (A->m <= 16) launch_arn<16>(*A, mode, st);
+    else launch_arn<32>(*A, mode, st);
+    return hipGetLastError();
+}
+hipError_t sem_launch_arn_finish(const double *partial, int64_t nblk, int nq, int pyth, double *out, hipStream_t st)
+{
+    if (nq < 1 || nq > ARN_MAXV + 1 || (pyth && nq < 2)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_arn_finish, dim3(1), dim3(RT), 0, st, partial, nblk, nq, pyth, out);
+    return hipGetLastError();
+}
 hipError_t sem_launch_hadamard(double *y, const double *a, const double *b, int64_t n, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
@@ -1187,34 +1308,18 @@ hipError_t sem_launch_corner(const CornerArgs *A, hipStream_t st)
     hipLaunchKernelGGL(k_corner, dim3((unsigned)A->nelv), dim3(VT), 0, st, *A);
     return hipGetLastError();
 }
-hipError_t sem_launch_vgather(const VGatherArgs *A, hipStream_t st)
-{
-    if (A->nv == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_vgather, dim3((unsigned)((A->nv + VT - 1) / VT)), dim3(VT), 0, st, *A);
-    return hipGetLastError();
-}
-// iters fixed-count Jacobi-CG steps on the coarse system from x = 0 (no host sync);
-// partial must hold 2 * ceil(nv / VT) values.
+// iters fixed-count Jacobi-CG steps on the coarse system from x = 0, two launches per
+// step and no host sync; partial must hold 3 * ceil(nv / VT) values.
 hipError_t sem_launch_coarse_cg(const CoarseArgs *A, int iters, hipStream_t st)
 {
     if (A->nv == 0) return hipSuccess;
+    if (A->width < 1 || A->nv > 0x7fffffffLL * VT) return hipErrorInvalidValue;
     const unsigned g = (unsigned)((A->nv + VT - 1) / VT);
     hipLaunchKernelGGL(k_ccg_start, dim3(g), dim3(VT), 0, st, *A);
-    hipLaunchKernelGGL(k_ccg_scalar, dim3(1), dim3(RT), 0, st, *A, (int64_t)g, 0);
     for (int it = 0; it < iters; ++it) {
-        hipLaunchKernelGGL(k_ccg_spmv, dim3(g), dim3(VT), 0, st, *A);
-        hipLaunchKernelGGL(k_ccg_scalar, dim3(1), dim3(RT), 0, st, *A, (int64_t)g, 1);
-        hipLaunchKernelGGL(k_ccg_update, dim3(g), dim3(VT), 0, st, *A);
-        hipLaunchKernelGGL(k_ccg_scalar, dim3(1), dim3(RT), 0, st, *A, (int64_t)g, 2);
-        if (it + 1 < iters) hipLaunchKernelGGL(k_ccg_dir, dim3(g), dim3(VT), 0, st, *A);
+        hipLaunchKernelGGL(k_ccg_spmv, dim3(g), dim3(VT), 0, st, *A, it);
+        hipLaunchKernelGGL(k_ccg_update, dim3(g), dim3(VT), 0, st, *A, it);
     }
-    return hipGetLastError();
-}
-hipError_t sem_launch_prolong(const ProlongArgs *A, hipStream_t st)
-{
-    const int64_t n = A->nelv * A->lx3;
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prolong, dim3((unsigned)((n + VT - 1) / VT)), dim3(VT), 0, st, *A);
     return hipGetLastError();
 }
 hipError_t sem_launch_probe(double *v, const double *phi, int c, int64_t nelv, int lx3, hipStream_t st)
