@@ -84,6 +84,8 @@ hipError_t sem_launch_mdot(const MdotArgs *, unsigned, hipStream_t);
 hipError_t sem_launch_comb(const CombArgs *, hipStream_t);
 hipError_t sem_launch_hadamard(double *, const double *, const double *, int64_t, hipStream_t);
 unsigned sem_arn_grid(int64_t n);
+hipError_t sem_launch_dcgs(const DcgsArgs *, int, hipStream_t);
+hipError_t sem_launch_dcgs_finish(const double *, int64_t, int, double *, hipStream_t);
 hipError_t sem_launch_arn(const ArnArgs *, int, hipStream_t);
 hipError_t sem_launch_arn_finish(const double *, int64_t, int, int, double *, hipStream_t);
 hipError_t sem_launch_corner(const CornerArgs *, hipStream_t);
@@ -2095,6 +2097,111 @@ static sem_status arnoldi_step(const VecCtx &X, const double *V, int64_t n, int 
     return SEM_OK;
 }
 
+// Apply the rotations 0..k-1 to column col (entries 0..k+1), then annihilate
+// col[k+1] with a new rotation k and rotate g.  False on a zero or non-finite pivot.
+static bool givens_column(double *col, int k, std::vector<double> &cs, std::vector<double> &sn,
+                          std::vector<double> &gv)
+{
+    for (int i = 0; i < k; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+    }
+    const double den = std::hypot(col[k], col[k + 1]);
+    if (!(den > 0.0) || !std::isfinite(den)) return false;
+    cs[k] = col[k] / den;
+    sn[k] = col[k + 1] / den;
+    col[k] = den;
+    col[k + 1] = 0.0;
+    gv[k + 1] = -sn[k] * gv[k];
+    gv[k] = cs[k] * gv[k];
+    return true;
+}
+
+// One GMRES cycle (restart m <= ARN_MAXV) with the delayed two-pass Gram-Schmidt
+// step: V_0 = r / beta on entry.  At step j the basis vector u_j = V_j has been
+// orthogonalised once; its second pass is made together with the first pass for
+// w = A M^{-1} u_j (two passes over V_0..V_j, one host sync).  u_j then becomes the
+// final q_j, and column j-1 of the Hessenberg matrix is completed with
+// u_j = Q a + rho q_j; column j is tentative until the next step, and the cycle's
+// last column is completed by one extra dot pass.  The stopping test uses the
+// tentative column (it differs from the final one at rounding level).  On return the
+// rotated columns 0..jj-1 are in H and g in gv.
+static sem_status gmres_cycle_dcgs(sem_coef c, sem_gs g, const sem_gmres_params *P, const VecCtx &X, double *V,
+                                   double *Z, int m, double beta, double bn, int &total, int &jj, bool &breakdown,
+                                   std::vector<double> &H, std::vector<double> &gv, std::vector<double> &cs,
+                                   std::vector<double> &sn, hipStream_t st)
+{
+    const int64_t n = X.n;
+    const int64_t G = sem_arn_grid(n);
+    std::vector<double> prev(m + 2, 0.0), col(m + 2, 0.0), t(m + 2, 0.0);
+    double prev_nu = 0.0;
+    std::fill(gv.begin(), gv.end(), 0.0);
+    jj = 0;
+    for (int j = 0; j < m && total < P->max_iter; ++j) {
+        double *Vj = V + (int64_t)j * n, *Vn = V + (int64_t)(j + 1) * n, *Zj = Z + (int64_t)j * n;
+        SEM_TRY(gmres_precond(c, g, P, Zj, Vj, st));
+        SEM_TRY(gmres_apply(c, g, Vn, Zj, st));
+        const int nq = 2 * j + 3;
+        DcgsArgs D{V, n, j, Vj, Vn, X.owner, X.out + nq, X.partial, n};
+        HIP_TRY(sem_launch_dcgs(&D, 0, st));
+        HIP_TRY(sem_launch_dcgs_finish(X.partial, G, j, X.out, st));
+        HIP_TRY(sem_launch_dcgs(&D, 1, st));
+        HIP_TRY(hipMemcpyAsync(X.h_out, X.out, sizeof(double) * (nq + 2 * j + 6), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        total += 1;
+        const double *a = X.h_out, *bq = X.h_out + j + 1, *cf = X.h_out + nq;
+        const double rho = cf[2 * j + 3], gam = cf[2 * j + 4], nu = cf[2 * j + 5];
+        if (j == 0) {
+            gv[0] = beta * rho;  // r = beta u_0 = beta rho q_0
+        } else {
+            for (int i = 0; i < j; ++i) col[i] = prev[i] + prev_nu * a[i];
+            col[j] = prev_nu * rho;
+            if (!givens_column(col.data(), j - 1, cs, sn, gv)) {
+                breakdown = true;
+                jj = j - 1;
+                return SEM_OK;
+            }
+            for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] = col[i];
+        }
+        // tentative column j: A z_j = Q b + gamma q_j + nu u_{j+1}
+        for (int i = 0; i < j; ++i) prev[i] = bq[i];
+        prev[j] = gam;
+        prev_nu = nu;
+        jj = j + 1;
+        for (int i = 0; i <= j; ++i) t[i] = prev[i];
+        for (int i = 0; i < j; ++i) {
+            const double tt = cs[i] * t[i] + sn[i] * t[i + 1];
+            t[i + 1] = -sn[i] * t[i] + cs[i] * t[i + 1];
+            t[i] = tt;
+        }
+        const double den = std::hypot(t[j], nu);
+        const double est = den > 0.0 ? std::fabs(nu / den * gv[j]) : 0.0;
+        const bool last = !(est > P->rtol * bn) || !(nu > 1e-300) || total >= P->max_iter || j == m - 1;
+        if (last) {
+            // complete column j: u_{j+1} = [q_0..q_j] a' + rho' q_{j+1}
+            ArnArgs A{V, n, j + 1, Vn, Vn, X.owner, nullptr, nullptr, X.partial, n};
+            HIP_TRY(sem_launch_arn(&A, 0, st));
+            HIP_TRY(sem_launch_arn_finish(X.partial, G, j + 2, 0, X.out, st));
+            HIP_TRY(hipMemcpyAsync(X.h_out, X.out, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            double rr = X.h_out[j + 1];
+            for (int i = 0; i <= j; ++i) rr = std::fma(-X.h_out[i], X.h_out[i], rr);
+            const double rho1 = rr > 0.0 ? std::sqrt(rr) : 0.0;
+            for (int i = 0; i <= j; ++i) col[i] = prev[i] + nu * X.h_out[i];
+            col[j + 1] = nu * rho1;
+            if (!givens_column(col.data(), j, cs, sn, gv)) {
+                breakdown = true;
+                jj = j;
+                return SEM_OK;
+            }
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = col[i];
+            return SEM_OK;
+        }
+    }
+    return SEM_OK;
+}
+
 static sem_status gmres_run(double *x, const double *b, sem_coef c, sem_gs g, const sem_gmres_params *P,
                             sem_pcg_info *info, hipStream_t st)
 {
@@ -2107,9 +2214,10 @@ static sem_status gmres_run(double *x, const double *b, sem_coef c, sem_gs g, co
         W.gm_hout = nullptr;
         W.gm_m = 0;
         SEM_TRY(dalloc(&W.gm, (size_t)(2 * m + 2) * n));
-        SEM_TRY(dalloc(&W.gm_part, std::max((size_t)PB * sem_vec_grid(n), (size_t)(ARN_MAXV + 1) * sem_arn_grid(n))));
-        SEM_TRY(dalloc(&W.gm_out, (size_t)2 * (m + 3)));
-        HIP_TRY(hipHostMalloc((void **)&W.gm_hout, sizeof(double) * 2 * (m + 3), hipHostMallocDefault));
+        SEM_TRY(dalloc(&W.gm_part, std::max((size_t)PB * sem_vec_grid(n), (size_t)(2 * ARN_MAXV + 3) * sem_arn_grid(n))));
+        const size_t nout = (size_t)std::max(2 * (m + 3), 4 * m + 16);
+        SEM_TRY(dalloc(&W.gm_out, nout));
+        HIP_TRY(hipHostMalloc((void **)&W.gm_hout, sizeof(double) * nout, hipHostMallocDefault));
         W.gm_m = m;
     }
     double *V = W.gm;                          // V_0 .. V_m
@@ -2137,52 +2245,56 @@ static sem_status gmres_run(double *x, const double *b, sem_coef c, sem_gs g, co
         cycles += 1;
         const double inv = 1.0 / beta;
         SEM_TRY(vcomb(X, V, nullptr, V, n, 1, &inv, 0, st));
-        std::fill(gv.begin(), gv.end(), 0.0);
-        gv[0] = beta;
         int jj = 0;
-        for (int j = 0; j < m && total < P->max_iter; ++j) {
-            double *Vj = V + (int64_t)j * n, *Vn = V + (int64_t)(j + 1) * n, *Zj = Z + (int64_t)j * n;
-            SEM_TRY(gmres_precond(c, g, P, Zj, Vj, st));
-            SEM_TRY(gmres_apply(c, g, Vn, Zj, st));
-            // classical Gram-Schmidt against V_0..V_j, twice; V_{j+1} normalised
-            double hn;
-            if (j + 1 <= ARN_MAXV) {
-                SEM_TRY(arnoldi_step(X, V, n, j + 1, Vn, W.gm_out, m + 3, h.data(), &hn, st));
-            } else {
-                SEM_TRY(vdots(X, V, n, j + 1, Vn, h.data(), st));
-                for (int i = 0; i <= j; ++i) h2[i] = -h[i];
-                SEM_TRY(vcomb(X, Vn, nullptr, V, n, j + 1, h2.data(), 1, st));
-                SEM_TRY(vdots(X, V, n, j + 1, Vn, h2.data(), st));
-                for (int i = 0; i <= j; ++i) {
-                    h[i] += h2[i];
-                    h2[i] = -h2[i];
+        if (m <= ARN_MAXV) {
+            SEM_TRY(gmres_cycle_dcgs(c, g, P, X, V, Z, m, beta, bn, total, jj, breakdown, H, gv, cs, sn, st));
+        } else {
+            std::fill(gv.begin(), gv.end(), 0.0);
+            gv[0] = beta;
+            for (int j = 0; j < m && total < P->max_iter; ++j) {
+                double *Vj = V + (int64_t)j * n, *Vn = V + (int64_t)(j + 1) * n, *Zj = Z + (int64_t)j * n;
+                SEM_TRY(gmres_precond(c, g, P, Zj, Vj, st));
+                SEM_TRY(gmres_apply(c, g, Vn, Zj, st));
+                // classical Gram-Schmidt against V_0..V_j, twice; V_{j+1} normalised
+                double hn;
+                if (j + 1 <= ARN_MAXV) {
+                    SEM_TRY(arnoldi_step(X, V, n, j + 1, Vn, W.gm_out, m + 3, h.data(), &hn, st));
+                } else {
+                    SEM_TRY(vdots(X, V, n, j + 1, Vn, h.data(), st));
+                    for (int i = 0; i <= j; ++i) h2[i] = -h[i];
+                    SEM_TRY(vcomb(X, Vn, nullptr, V, n, j + 1, h2.data(), 1, st));
+                    SEM_TRY(vdots(X, V, n, j + 1, Vn, h2.data(), st));
+                    for (int i = 0; i <= j; ++i) {
+                        h[i] += h2[i];
+                        h2[i] = -h2[i];
+                    }
+                    SEM_TRY(vcomb(X, Vn, nullptr, V, n, j + 1, h2.data(), 1, st));
+                    double hh;
+                    SEM_TRY(vdots(X, Vn, n, 1, Vn, &hh, st));
+                    hn = std::sqrt(hh);
+                    if (hn > 1e-300) {
+                        const double ih = 1.0 / hn;
+                        SEM_TRY(vcomb(X, Vn, nullptr, Vn, n, 1, &ih, 0, st));
+                    }
                 }
-                SEM_TRY(vcomb(X, Vn, nullptr, V, n, j + 1, h2.data(), 1, st));
-                double hh;
-                SEM_TRY(vdots(X, Vn, n, 1, Vn, &hh, st));
-                hn = std::sqrt(hh);
-                if (hn > 1e-300) {
-                    const double ih = 1.0 / hn;
-                    SEM_TRY(vcomb(X, Vn, nullptr, Vn, n, 1, &ih, 0, st));
+                total += 1;
+                jj = j + 1;
+                // rotate column j with the earlier Givens rotations, then annihilate H[j+1][j]
+                for (int i = 0; i < j; ++i) {
+                    const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+                    h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+                    h[i] = t;
                 }
+                const double den = std::hypot(h[j], hn);
+                if (!(den > 0.0) || !std::isfinite(den)) { breakdown = true; jj = j; break; }
+                cs[j] = h[j] / den;
+                sn[j] = hn / den;
+                h[j] = den;
+                gv[j + 1] = -sn[j] * gv[j];
+                gv[j] = cs[j] * gv[j];
+                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
+                if (std::fabs(gv[j + 1]) <= P->rtol * bn || hn <= 1e-300) break;  // converged or invariant space
             }
-            total += 1;
-            jj = j + 1;
-            // rotate column j with the earlier Givens rotations, then annihilate H[j+1][j]
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * h[i] + sn[i] * h[i + 1];
-                h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
-                h[i] = t;
-            }
-            const double den = std::hypot(h[j], hn);
-            if (!(den > 0.0) || !std::isfinite(den)) { breakdown = true; jj = j; break; }
-            cs[j] = h[j] / den;
-            sn[j] = hn / den;
-            h[j] = den;
-            gv[j + 1] = -sn[j] * gv[j];
-            gv[j] = cs[j] * gv[j];
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
-            if (std::fabs(gv[j + 1]) <= P->rtol * bn || hn <= 1e-300) break;  // converged or invariant space
         }
         if (jj == 0) break;
         // y = R^{-1} g (upper triangular), x += Z y

@@ -177,6 +177,26 @@ struct ArnArgs {
     int64_t n;
 };
 
+// Delayed two-pass classical Gram-Schmidt step: the second pass for the previous
+// basis vector u (orthogonalised once, one step ago) is made in the same passes as
+// the first pass for the new vector w.  With Q = V_0..V_{j-1} (orthonormal):
+//   dots:   a = Q^T u, (u, u), b = Q^T w, (u, w), (w, w)  -> partial rows
+//           [a (j), (u,u), b (j), (u,w), (w,w)] of length 2 j + 3;
+//   update: u <- (u - Q a) / rho                          (the final q_j)
+//           w <- (w - Q c - delta u) / nu                  (the next u)
+// with the coefficients in coef: [a (j), c (j), 1/rho, delta, 1/nu].
+struct DcgsArgs {
+    const double *V;       // basis vector i at V + i * ld
+    int64_t ld;
+    int j;                 // finished basis vectors, 0..ARN_MAXV - 1
+    double *u;
+    double *w;
+    const uint8_t *owner;  // one copy per global id
+    const double *coef;    // update pass
+    double *partial;       // dots pass: [2 j + 3][grid]
+    int64_t n;
+};
+
 // ---------------------------------------------------------------- two-level Schwarz
 // out[e][c] = sum over element e's points p of phi[c][p] v[e][p] (owner[p] if owner).
 struct CornerArgs {

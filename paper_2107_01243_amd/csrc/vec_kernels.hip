@@ -403,6 +403,143 @@ __global__ __launch_bounds__(RT) void k_arn_finish(const double *partial, int64_
     }
 }
 
+// Dots pass of the delayed Gram-Schmidt step (see DcgsArgs).
+template <int MV>
+__global__ __launch_bounds__(VT) void k_dcgs_dots(DcgsArgs A, int64_t chunk)
+{
+    constexpr int NR = 2 * MV + 3;
+    const int j = A.j;
+    double ua[MV], wb[MV], uu = 0.0, uw = 0.0, ww = 0.0;
+#pragma unroll
+    for (int i = 0; i < MV; ++i) ua[i] = wb[i] = 0.0;
+    const int64_t t0 = (int64_t)blockIdx.x * chunk;
+    const int64_t t1 = min(A.n, t0 + chunk);
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += VT) {
+        double v[MV];
+#pragma unroll
+        for (int i = 0; i < MV; ++i) v[i] = (i < j) ? A.V[i * A.ld + t] : 0.0;
+        const double u = A.u[t], w = A.w[t];
+        const bool own = A.owner[t] != 0;
+        const double uo = own ? u : 0.0, wo = own ? w : 0.0;
+#pragma unroll
+        for (int i = 0; i < MV; ++i)
+            if (i < j) {
+                ua[i] = fma(v[i], uo, ua[i]);
+                wb[i] = fma(v[i], wo, wb[i]);
+            }
+        uu = fma(u, uo, uu);
+        uw = fma(u, wo, uw);
+        ww = fma(w, wo, ww);
+    }
+    // rows: a_0..a_{j-1}, (u,u), b_0..b_{j-1}, (u,w), (w,w)
+    __shared__ double sh[VT / 64][NR];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    auto put = [&](int q, double x) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) sh[wave][q] = x;
+    };
+#pragma unroll
+    for (int i = 0; i < MV; ++i)
+        if (i < j) {
+            put(i, ua[i]);
+            put(j + 1 + i, wb[i]);
+        }
+    put(j, uu);
+    put(2 * j + 1, uw);
+    put(2 * j + 2, ww);
+    __syncthreads();
+    const int q = threadIdx.x;
+    if (q < 2 * j + 3) {
+        double x = 0.0;
+#pragma unroll
+        for (int w4 = 0; w4 < VT / 64; ++w4) x += sh[w4][q];
+        A.partial[(int64_t)q * gridDim.x + blockIdx.x] = x;
+    }
+}
+
+// Update pass of the delayed Gram-Schmidt step (see DcgsArgs).
+template <int MV>
+__global__ __launch_bounds__(VT) void k_dcgs_update(DcgsArgs A, int64_t chunk)
+{
+    const int j = A.j;
+    const double *cf = A.coef;
+    double ca[MV], cc[MV];
+#pragma unroll
+    for (int i = 0; i < MV; ++i) {
+        ca[i] = (i < j) ? cf[i] : 0.0;
+        cc[i] = (i < j) ? cf[j + i] : 0.0;
+    }
+    const double irho = cf[2 * j], del = cf[2 * j + 1], inu = cf[2 * j + 2];
+    const int64_t t0 = (int64_t)blockIdx.x * chunk;
+    const int64_t t1 = min(A.n, t0 + chunk);
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += VT) {
+        double v[MV];
+#pragma unroll
+        for (int i = 0; i < MV; ++i) v[i] = (i < j) ? A.V[i * A.ld + t] : 0.0;
+        const double u = A.u[t];
+        double q = u, y = A.w[t];
+#pragma unroll
+        for (int i = 0; i < MV; ++i)
+            if (i < j) {
+                q = fma(-ca[i], v[i], q);
+                y = fma(-cc[i], v[i], y);
+            }
+        y = fma(-del, u, y);
+        A.u[t] = q * irho;
+        A.w[t] = y * inu;
+    }
+}
+
+// Reduction of the dots pass, one wave per row in a fixed order: out[0..2j+3) = the
+// row sums; then at out + 2 j + 3 the update coefficients and the step's scalars:
+//   rho^2 = (u,u) - |a|^2,  gamma = ((u,w) - a.b) / rho,  delta = gamma / rho,
+//   nu^2 = (w,w) - |b|^2 - gamma^2  (Pythagorean identities),  c = b - delta a;
+//   [a (j), c (j), 1/rho, delta, 1/nu, rho, gamma, nu]  (reciprocals 0 when not positive).
+__global__ __launch_bounds__(RT) void k_dcgs_finish(const double *partial, int64_t nblk, int j, double *out)
+{
+    __shared__ double sh[2 * ARN_MAXV + 3];
+    const int nq = 2 * j + 3;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = wave; q < nq; q += RT / 64) {
+        double s = 0.0;
+        for (int64_t b = lane; b < nblk; b += 64) s += partial[(int64_t)q * nblk + b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) {
+            out[q] = s;
+            sh[q] = s;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double *a = sh, *b = sh + j + 1;
+        double aa = sh[j], ab = sh[2 * j + 1], bb = sh[2 * j + 2];
+        for (int i = 0; i < j; ++i) {
+            aa = fma(-a[i], a[i], aa);
+            ab = fma(-a[i], b[i], ab);
+            bb = fma(-b[i], b[i], bb);
+        }
+        const double rho = aa > 0.0 ? sqrt(aa) : 0.0;
+        const double gam = rho > 0.0 ? ab / rho : 0.0;
+        const double del = rho > 0.0 ? gam / rho : 0.0;
+        double nn = fma(-gam, gam, bb);
+        nn = nn > 0.0 ? nn : 0.0;
+        const double nu = sqrt(nn);
+        double *cf = out + nq;
+        for (int i = 0; i < j; ++i) {
+            cf[i] = a[i];
+            cf[j + i] = fma(-del, a[i], b[i]);
+        }
+        cf[2 * j] = rho > 0.0 ? 1.0 / rho : 0.0;
+        cf[2 * j + 1] = del;
+        cf[2 * j + 2] = nu > 0.0 ? 1.0 / nu : 0.0;
+        cf[2 * j + 3] = rho;
+        cf[2 * j + 4] = gam;
+        cf[2 * j + 5] = nu;
+    }
+}
+
 // y = a * b pointwise (point-Jacobi preconditioning of a Krylov vector).
 __global__ __launch_bounds__(VT) void k_hadamard(double *y, const double *a, const double *b, int64_t n)
 {
@@ -1146,6 +1283,14 @@ static unsigned arn_grid(int64_t n)
     return (unsigned)(g < 1 ? 1 : g);
 }
 template <int MV>
+static void launch_dcgs(const DcgsArgs &A, int pass, hipStream_t st)
+{
+    const unsigned g = arn_grid(A.n);
+    const int64_t c = arn_chunk(A.n);
+    if (pass == 0) hipLaunchKernelGGL((k_dcgs_dots<MV>), dim3(g), dim3(VT), 0, st, A, c);
+    else hipLaunchKernelGGL((k_dcgs_update<MV>), dim3(g), dim3(VT), 0, st, A, c);
+}
+template <int MV>
 static void launch_arn(const ArnArgs &A, int mode, hipStream_t st)
 {
     const unsigned g = arn_grid(A.n);
@@ -1279,6 +1424,21 @@ hipError_t sem_launch_comb(const CombArgs *A, hipStream_t st)
     return hipGetLastError();
 }
 unsigned sem_arn_grid(int64_t n) { return arn_grid(n); }
+hipError_t sem_launch_dcgs(const DcgsArgs *A, int pass, hipStream_t st)
+{
+    if (A->j < 0 || A->j >= ARN_MAXV || pass < 0 || pass > 1 || A->n < 1) return hipErrorInvalidValue;
+    if (pass == 1 && !A->coef) return hipErrorInvalidValue;
+    if (A->j <= 8) launch_dcgs<8>(*A, pass, st);
+    else if (A->j <= 16) launch_dcgs<16>(*A, pass, st);
+    else launch_dcgs<32>(*A, pass, st);
+    return hipGetLastError();
+}
+hipError_t sem_launch_dcgs_finish(const double *partial, int64_t nblk, int j, double *out, hipStream_t st)
+{
+    if (j < 0 || j >= ARN_MAXV) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dcgs_finish, dim3(1), dim3(RT), 0, st, partial, nblk, j, out);
+    return hipGetLastError();
+}
 hipError_t sem_launch_arn(const ArnArgs *A, int mode, hipStream_t st)
 {
     if (A->m < 1 || A->m > ARN_MAXV || mode < 0 || mode > 2 || A->n < 1) return hipErrorInvalidValue;
