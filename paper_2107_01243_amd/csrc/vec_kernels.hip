@@ -1269,11 +1269,11 @@ static hipError_t launch_gs_t(const GsArgs<T> *A, hipStream_t st)
     return hipGetLastError();
 }
 // Workgroups of the Arnoldi passes: contiguous chunks of whole 256-point rows, at
-// most 2048 workgroups (a few per CU), so the partial rows stay short.
+// most 1024 workgroups (four per CU), so the partial rows stay short.
 static int64_t arn_chunk(int64_t n)
 {
     const int64_t rows = (n + VT - 1) / VT;
-    const int64_t per = (rows + 2047) / 2048;
+    const int64_t per = (rows + 1023) / 1024;
     return (per < 1 ? 1 : per) * VT;
 }
 static unsigned arn_grid(int64_t n)
