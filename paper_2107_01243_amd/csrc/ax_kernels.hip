@@ -343,10 +343,15 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo<LX, T>
     for (int f = 0; f < 6; ++f) load_g<LX, T>(g[f], A.G + f * A.n + row, act);
     RowCoef<LX, T, GEN> c;
     load_coef<LX, T, GEN>(c, A, row, act);
+    // the next field's row is loaded while the current one is processed
+    T un[LX];
+    load_row<LX, T>(un, A.u + row, act);
 #pragma unroll 1
     for (int f = 0; f < NF; ++f) {
         T u[LX];
-        load_row<LX, T>(u, A.u + f * A.n + row, act);
+#pragma unroll
+        for (int k = 0; k < LX; ++k) u[k] = un[k];
+        if (f + 1 < NF) load_row<LX, T>(un, A.u + (f + 1) * A.n + row, act);
         T ur[LX], us[LX], ut[LX];
         grad<LX, T>(D, u, s0, s1, a, b, ur, us, ut);
         apply_G<LX, T, GEN>(g, c, A.h1s, ur, us, ut);
@@ -440,8 +445,6 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DE
 }
 
 // ------------------------------------------------------------------ Schwarz local solves
-// Transform one pencil of the element cube along direction DIR (0: i, 1: j, 2: k):
-// forward out_m = sum_l S[l][m] in_l (S^T), inverse out_l = sum_m S[l][m] in_m (S).
 // y = M x along one pencil, M row-major (a copy of S or of its transpose in LDS),
 // each y[m] summed over ascending l.
 template <int LX>
