@@ -224,8 +224,9 @@ sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef,
  * The paper's pressure equation is solved with GMRES (Section 4, Table 2).
  * Flexible GMRES(m) (Saad, Algorithm 9.6): right preconditioning with a
  * preconditioner that may change between steps, Arnoldi in the unique-node inner
- * product by classical Gram-Schmidt applied twice, Givens rotations, restart after m
- * steps from the true residual b - A x.  Solves mask QQ^T A_L(h1, h2) x = b for one
+ * product by classical Gram-Schmidt applied twice (for m <= 32 each vector's second
+ * pass is made in the same passes over the data as the next vector's first), Givens
+ * rotations, restart after m steps from the true residual b - A x.  Solves mask QQ^T A_L(h1, h2) x = b for one
  * field (x, b device FP64, b assembled and masked).  Converged when |b - A x| <= rtol |b|
  * for the true residual (checked at every restart and at exit).  Device memory:
  * (2 m + 2) vectors of n_p values, kept by the coef handle between calls. */
