@@ -431,6 +431,15 @@ def main():
                                 "frac": round(bpp * P.n / t / 1e9 / HBM_PEAK_GBS, 4)}
                             for k, (t, bpp) in kern.items()}
     out["pcg_fp64_gpoint_iters_per_s"] = round(P.n * out["pcg_fp64_iters"] / out["pcg_fp64_solve_s"] / 1e9, 3)
+    # the paper's own numbers, on its own hardware (context only)
+    out["paper_context"] = {
+        "ax_fp64_fraction_of_peak": "more than 10% on most platforms (lx=10, 128-8192 elements)",
+        "ax_cpu_socket_gdofs_derived": 0.45,
+        "ax_cpu_hardware": "one 16-core Intel Xeon E5-2698v3 socket, 2.3 GHz (Cray XC40); GDOF/s derived from "
+                           ">10% of its 589 GFLOP/s FP64 peak at ~131 flop per point",
+        "solver_effective_GBs": 84,
+        "solver_hardware": "Cray XC40 node, 2x E5-2698v3, STREAM triad 90 GB/s (TGV, FP64)",
+    }
     if pres is not None:
         out.update({
             "pressure_gmres_schwarz_solve_s": round(pres[0], 4),
