@@ -386,7 +386,8 @@ def test_gmres_fixed_steps_vs_oracle():
     bl = workloads.uniform(P.n, workloads.SEED_RHS)
     bo = O.assemble_rhs(bl)
     b = P.assemble(to_dev(bl))
-    for restart, k in ((30, 1), (30, 2), (30, 7), (30, 25), (30, 30), (30, 31), (60, 7), (60, 45)):
+    for restart, k in ((30, 1), (30, 2), (30, 7), (30, 25), (30, 30), (30, 31), (1, 4), (2, 5), (32, 33),
+                       (60, 7), (60, 45)):
         xo, io = O.gmres(bo, rtol=1e-30, restart=restart, max_iter=k)
         x, info = P.gmres(b, rtol=1e-30, restart=restart, max_iter=k, raise_on_fail=False)
         assert info["iters"] == io["iters"] == k
