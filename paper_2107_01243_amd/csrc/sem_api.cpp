@@ -80,7 +80,6 @@ hipError_t sem_launch_cg_resume(const CgFinishArgs *, const int *, hipStream_t);
 hipError_t sem_launch_rel_resume(const CgFinishArgs *, RelState *, int, hipStream_t);
 hipError_t sem_launch_add_f32(double *, const float *, const int *, int64_t, int, hipStream_t);
 hipError_t sem_launch_dots_finish(const double *, int64_t, int, double *, hipStream_t);
-hipError_t sem_launch_mdot(const MdotArgs *, unsigned, hipStream_t);
 hipError_t sem_launch_comb(const CombArgs *, hipStream_t);
 hipError_t sem_launch_hadamard(double *, const double *, const double *, int64_t, hipStream_t);
 unsigned sem_arn_grid(int64_t n);
@@ -1576,7 +1575,7 @@ static void proj_free(sem_proj P)
 struct VecCtx {
     int64_t n;
     const uint8_t *owner;  // unique-node inner product: one copy of each global id
-    double *partial;       // device [PB][vec grid]
+    double *partial;       // device partial rows of the dot passes
     double *out;           // device results
     double *h_out;         // pinned mirror
 };
@@ -1585,11 +1584,18 @@ struct VecCtx {
 static sem_status vdots(const VecCtx &X, const double *V, int64_t ld, int l, const double *v, double *host_out,
                         hipStream_t st)
 {
-    const unsigned grid = sem_vec_grid(X.n);
-    for (int i0 = 0; i0 < l; i0 += PB) {
-        MdotArgs A{V + (int64_t)i0 * ld, ld, std::min(PB, l - i0), v, X.owner, X.partial, X.n};
-        HIP_TRY(sem_launch_mdot(&A, grid, st));
-        HIP_TRY(sem_launch_dots_finish(X.partial, grid, A.l, X.out + i0, st));
+    if (X.n == 0) {
+        std::fill(host_out, host_out + l, 0.0);
+        return SEM_OK;
+    }
+    // up to ARN_MAXV vectors per pass over the data; each pass's reduction also
+    // yields (v, v) one slot past its rows, overwritten by the next pass
+    const int64_t G = sem_arn_grid(X.n);
+    for (int i0 = 0; i0 < l; i0 += ARN_MAXV) {
+        const int cl = std::min(ARN_MAXV, l - i0);
+        ArnArgs A{V + (int64_t)i0 * ld, ld, cl, v, nullptr, X.owner, nullptr, nullptr, X.partial, X.n};
+        HIP_TRY(sem_launch_arn(&A, 0, st));
+        HIP_TRY(sem_launch_arn_finish(X.partial, G, cl + 1, 0, X.out + i0, st));
     }
     HIP_TRY(hipMemcpyAsync(X.h_out, X.out, sizeof(double) * l, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1719,8 +1725,8 @@ sem_status sem_proj_create(sem_coef coef, sem_mesh msh, sem_space Xh, sem_gs gs,
         if (e == SEM_OK) e = dalloc(&P->r, n);
         if (e == SEM_OK) e = dalloc(&P->d, n);
         if (e == SEM_OK) e = dalloc(&P->w, n);
-        if (e == SEM_OK) e = dalloc(&P->partial, (size_t)PB * sem_vec_grid(n));
-        if (e == SEM_OK) e = dalloc(&P->out, P->m);
+        if (e == SEM_OK) e = dalloc(&P->partial, (size_t)(ARN_MAXV + 1) * sem_arn_grid(n));
+        if (e == SEM_OK) e = dalloc(&P->out, P->m + 1);
         if (e == SEM_OK && hipHostMalloc((void **)&P->h_out, sizeof(double) * P->m, hipHostMallocDefault) != hipSuccess)
             e = fail(SEM_ERR_OOM, "pinned host allocation failed");
     }

@@ -133,16 +133,6 @@ struct DotArgs {
 // Projection onto previous solutions: up to PB basis vectors per launch.
 constexpr int PB = 8;
 
-// partial[i][block] = sum over owned points of V_i . v   (i < l)
-struct MdotArgs {
-    const double *V;      // l vectors, V_i = V + i * ld
-    int64_t ld;
-    int l;
-    const double *v;
-    const uint8_t *owner;
-    double *partial;      // [l][grid]
-    int64_t n;
-};
 
 // y = sum_i c_i V_i (mode 0), y += sum_i c_i V_i (mode 1), y = src + sum_i c_i V_i (mode 2)
 struct CombArgs {

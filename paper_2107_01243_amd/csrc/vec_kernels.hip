@@ -256,39 +256,6 @@ __global__ __launch_bounds__(VT) void k_gs_entries(GsArgs<T> A)
 }
 
 // ------------------------------------------------------------------ projection space
-// Inner products of one vector with up to PB basis vectors in one pass over the
-// data (unique-node product: owned points only).  Per-wave butterflies, then the
-// waves in order: deterministic.
-__global__ __launch_bounds__(VT) void k_mdot(MdotArgs A)
-{
-    __shared__ double sh[VT / 64][PB];
-    double acc[PB];
-#pragma unroll
-    for (int i = 0; i < PB; ++i) acc[i] = 0.0;
-    const int64_t t_end = min(A.n, (int64_t)(blockIdx.x + 1) * CHUNK);
-    for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x; t < t_end; t += VT) {
-        const double o = A.owner[t] ? A.v[t] : 0.0;
-#pragma unroll
-        for (int i = 0; i < PB; ++i)
-            if (i < A.l) acc[i] = fma(A.V[i * A.ld + t], o, acc[i]);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < PB; ++i) {
-        double x = acc[i];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (lane == 0) sh[wave][i] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x < A.l) {
-        double x = 0.0;
-#pragma unroll
-        for (int q = 0; q < VT / 64; ++q) x += sh[q][threadIdx.x];
-        A.partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = x;
-    }
-}
-
 // Linear combination of up to PB basis vectors (coefficients by value).
 __global__ __launch_bounds__(VT) void k_comb(CombArgs A)
 {
@@ -1408,12 +1375,6 @@ hipError_t sem_launch_cg_replace_f64(const double *r, const double *dinv, const 
 hipError_t sem_launch_cg_resume(const CgFinishArgs *F, const int *redo, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cg_resume, dim3(1), dim3(RT), 0, st, *F, redo);
-    return hipGetLastError();
-}
-hipError_t sem_launch_mdot(const MdotArgs *A, unsigned grid, hipStream_t st)
-{
-    if (A->l < 1 || A->l > PB || (int64_t)grid * CHUNK < A->n) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_mdot, dim3(grid), dim3(VT), 0, st, *A);
     return hipGetLastError();
 }
 hipError_t sem_launch_comb(const CombArgs *A, hipStream_t st)
