@@ -895,12 +895,56 @@ __global__ __launch_bounds__(VT) void k_cg1_update(Cg1UpdateArgs A)
 }
 
 // End of one CG iteration: beta = rz_new / rz_old, convergence and iteration cap.
+// Two sums of nblk partials in one pass, fixed order: lane t accumulates entries
+// t, t + NTH, ... of both arrays (four interleaved accumulators each, eight loads in
+// flight), a butterfly per wave, then the NTH / 64 wave sums in order.  Every lane
+// gets both results.
+template <int NTH>
+__device__ void block_sum2_fixed(const double *pa, const double *pb, int64_t nblk, double *sh, double &ra,
+                                 double &rb)
+{
+    const int tid = threadIdx.x;
+    double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t q = tid;
+    for (; q + 3 * NTH < nblk; q += 4 * NTH) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] += pa[q + u * NTH];
+            b[u] += pb[q + u * NTH];
+        }
+    }
+    for (; q < nblk; q += NTH) {
+        a[0] += pa[q];
+        b[0] += pb[q];
+    }
+    double x = (a[0] + a[1]) + (a[2] + a[3]), y = (b[0] + b[1]) + (b[2] + b[3]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        x += __shfl_xor(x, off, 64);
+        y += __shfl_xor(y, off, 64);
+    }
+    if ((tid & 63) == 0) {
+        sh[2 * (tid >> 6)] = x;
+        sh[2 * (tid >> 6) + 1] = y;
+    }
+    __syncthreads();
+    ra = 0.0;
+    rb = 0.0;
+#pragma unroll
+    for (int w = 0; w < NTH / 64; ++w) {
+        ra += sh[2 * w];
+        rb += sh[2 * w + 1];
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(RT) void k_cg_finish(CgFinishArgs A)
 {
-    __shared__ double sh[RT];
+    __shared__ double sh[2 * (RT / 64)];
     for (int f = 0; f < A.nfields; ++f) {
-        const double rz = block_sum_fixed<RT>(A.partial + (0 * A.nfields + f) * A.nblk, A.nblk, sh);
-        const double rr = block_sum_fixed<RT>(A.partial + (1 * A.nfields + f) * A.nblk, A.nblk, sh);
+        double rz, rr;
+        block_sum2_fixed<RT>(A.partial + (0 * A.nfields + f) * A.nblk, A.partial + (1 * A.nfields + f) * A.nblk,
+                             A.nblk, sh, rz, rr);
         if (threadIdx.x == 0) {
             CgScalars &s = A.scal[f];
             if (!s.stop) {
