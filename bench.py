@@ -87,9 +87,18 @@ def cpu_baseline(wl, seconds=15.0):
         reps += 1
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = min(cores, os.cpu_count() or cores)
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": wl.n_local * reps / t / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
             "sample": f"{reps} oracle ax_helm applications on the full 32^3 lx=8 curved mesh "
-                      f"({wl.n_local} local points), FP64, {t:.1f}s"}
+                      f"({wl.n_local} local points), FP64, {t:.1f}s, {cores} threads of {model} "
+                      f"({os.cpu_count()} logical CPUs visible)"}
 
 
 def main():
