@@ -43,7 +43,7 @@ constexpr int RT = 1024;  // lanes of the single-workgroup reduction kernels
 #endif
 constexpr int GEPL = SEM_GS_EPL;  // 64-entry segments per wave of the entry-parallel gs
 #ifndef SEM_UPD32
-#define SEM_UPD32 4
+#define SEM_UPD32 8
 #endif
 // Points per lane of one CG-update workgroup, per precision: an FP32 chunk moves half
 // the bytes of an FP64 one, so it takes more points to amortise the workgroup's
