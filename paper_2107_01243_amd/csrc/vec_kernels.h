@@ -130,9 +130,9 @@ struct DotArgs {
     int nfields;
 };
 
-// Projection onto previous solutions: up to PB basis vectors per launch.
+// Linear combinations of basis vectors (projection space, GMRES solution update):
+// up to PB vectors per launch, coefficients by value.
 constexpr int PB = 8;
-
 
 // y = sum_i c_i V_i (mode 0), y += sum_i c_i V_i (mode 1), y = src + sum_i c_i V_i (mode 2)
 struct CombArgs {

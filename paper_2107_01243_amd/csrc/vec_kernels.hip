@@ -255,7 +255,7 @@ __global__ __launch_bounds__(VT) void k_gs_entries(GsArgs<T> A)
     }
 }
 
-// ------------------------------------------------------------------ projection space
+// ------------------------------------------------------------------ basis combinations
 // Linear combination of up to PB basis vectors (coefficients by value).
 __global__ __launch_bounds__(VT) void k_comb(CombArgs A)
 {
@@ -515,8 +515,9 @@ __global__ __launch_bounds__(VT) void k_hadamard(double *y, const double *a, con
 }
 
 // ------------------------------------------------------------------ two-level Schwarz
-// Per element, the eight weighted sums against the trilinear corner functions (the
-// restriction R0 = P^T, and the Galerkin products P_e^T A_e P_e from probe vectors).
+// Per element, the eight weighted sums against the trilinear corner functions (used at
+// setup for the Galerkin products P_e^T A_e P_e from probe vectors; the restriction
+// P^T r of an application is formed inside the local-solve kernel).
 __global__ __launch_bounds__(VT) void k_corner(CornerArgs A)
 {
     __shared__ double sh[8][VT / 64];
