@@ -21,12 +21,14 @@
 
 namespace semh {
 
-void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn)
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn, int64_t grain)
 {
     unsigned nt = std::thread::hardware_concurrency();
     if (nt == 0) nt = 1;
     if (nt > 32) nt = 32;
-    if (n < 65536 || nt == 1) {
+    if (grain < 1) grain = 1;
+    nt = (unsigned)std::min<int64_t>(nt, std::max<int64_t>(1, n / grain));
+    if (nt == 1) {
         fn(0, n);
         return;
     }
@@ -135,7 +137,7 @@ void box_mesh(int nx, int ny, int nz, int lx, double eps, const double *xi, int6
                         }
                     }
         }
-    });
+    }, 256);
 }
 
 // Bucket local indices by global id; returns false (with msg) on invalid input.

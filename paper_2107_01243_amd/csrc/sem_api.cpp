@@ -89,6 +89,7 @@ hipError_t sem_launch_arn(const ArnArgs *, int, hipStream_t);
 hipError_t sem_launch_arn_finish(const double *, int64_t, int, int, double *, hipStream_t);
 hipError_t sem_launch_corner(const CornerArgs *, hipStream_t);
 hipError_t sem_launch_coarse_cg(const CoarseArgs *, int, hipStream_t);
+hipError_t sem_launch_elem_gb(const double *, const double *, double *, int64_t, int, hipStream_t);
 hipError_t sem_launch_probe(double *, const double *, int, int64_t, int, hipStream_t);
 hipError_t sem_launch_residual(double *, const double *, const double *, const double *, int64_t, int,
                                hipStream_t);
@@ -1846,10 +1847,20 @@ static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
     const int lx = c->lx, N = lx - 1, lx3 = lx * lx * lx;
     const int64_t E = c->nelv, n = c->n;
     const sem_space Xh = c->Xh;
-    // element lengths: L_d = 2 / sqrt(mean over the element of G_dd / B)
-    std::vector<double> G((size_t)3 * n), B(n);
-    HIP_TRY(hipMemcpy(G.data(), c->G, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(B.data(), c->B, sizeof(double) * n, hipMemcpyDeviceToHost));
+    // element lengths: L_d = 2 / sqrt(mean over the element of G_dd / B), the sums
+    // formed on the device
+    std::vector<double> gb((size_t)3 * E);
+    {
+        double *d_gb = nullptr;
+        SEM_TRY(dalloc(&d_gb, gb.size()));
+        const hipError_t e1 = sem_launch_elem_gb(c->G, c->B, d_gb, E, lx3, st);
+        const hipError_t e2 = e1 == hipSuccess
+                                  ? hipMemcpyAsync(gb.data(), d_gb, sizeof(double) * gb.size(), hipMemcpyDeviceToHost, st)
+                                  : e1;
+        const hipError_t e3 = e2 == hipSuccess ? hipStreamSynchronize(st) : e2;
+        dfree(d_gb);
+        HIP_TRY(e3);
+    }
     std::vector<double> Kref((size_t)lx * lx, 0.0);
     for (int m = 0; m < lx; ++m)
         for (int q = 0; q < lx; ++q)
@@ -1860,9 +1871,7 @@ static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
         std::vector<double> a((size_t)lx * lx), V((size_t)lx * lx), l(lx), M(lx);
         for (int64_t e = e0; e < e1; ++e) {
             for (int d = 0; d < 3; ++d) {
-                double sum = 0.0;
-                for (int p = 0; p < lx3; ++p) sum += G[(size_t)d * n + e * lx3 + p] / B[e * lx3 + p];
-                const double L = 2.0 / std::sqrt(sum / lx3), J = L / 2.0, h = J * dref;
+                const double L = 2.0 / std::sqrt(gb[(size_t)e * 3 + d] / lx3), J = L / 2.0, h = J * dref;
                 for (int i = 0; i < lx; ++i) M[i] = Xh->w[i] * J;
                 M[0] += h / 2.0;
                 M[N] += h / 2.0;
@@ -1880,7 +1889,7 @@ static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
                 for (int m = 0; m < lx; ++m) lam[((size_t)e * 3 + d) * lx + m] = l[m];
             }
         }
-    });
+    }, 64);
     // trilinear corner functions at the GLL points, corner c = a + 2 b + 4 cc
     std::vector<double> phi((size_t)8 * lx3);
     for (int cc = 0; cc < 2; ++cc)
@@ -1961,37 +1970,58 @@ static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
         for (int64_t e = 0; e < E; ++e)
             for (int c2 = 0; c2 < 8; ++c2) Ae[(size_t)e * 64 + c2 * 8 + c8] = pe[e * 8 + c2];
     }
-    // assemble: rows ascending, columns ascending, duplicates summed in element order;
-    // Dirichlet vertices keep an identity row
-    struct Tri { int64_t r, c, e; double v; };
-    std::vector<Tri> tri;
-    tri.reserve((size_t)E * 64 + nv);
-    for (int64_t e = 0; e < E; ++e)
-        for (int c2 = 0; c2 < 8; ++c2)
+    // assemble row by row (rows in parallel): row v sums, per column, the element
+    // blocks of the elements at v in ascending element order (v_idx lists them so);
+    // columns ascending; Dirichlet rows and columns dropped, Dirichlet vertices keep
+    // an identity row
+    int64_t maxdeg = 1;
+    for (int64_t v = 0; v < nv; ++v) maxdeg = std::max<int64_t>(maxdeg, vptr[v + 1] - vptr[v]);
+    auto row_entries = [&](int64_t v, int32_t *cols, double *vals) -> int {
+        if (vdir[v]) {
+            cols[0] = (int32_t)v;
+            vals[0] = 1.0;
+            return 1;
+        }
+        int k = 0;
+        for (int64_t q = vptr[v]; q < vptr[v + 1]; ++q) {
+            const int64_t e = vidx[q] / 8;
+            const int c2 = (int)(vidx[q] % 8);
             for (int c8 = 0; c8 < 8; ++c8) {
-                const int64_t r = cvert[e * 8 + c2], cc = cvert[e * 8 + c8];
-                if (vdir[r] || vdir[cc]) continue;
-                tri.push_back({r, cc, e, Ae[(size_t)e * 64 + c2 * 8 + c8]});
+                const int32_t cc = cvert[e * 8 + c8];
+                if (vdir[cc]) continue;
+                int i = 0;
+                while (i < k && cols[i] != cc) ++i;
+                if (i == k) {
+                    cols[k] = cc;
+                    vals[k] = 0.0;
+                    ++k;
+                }
+                vals[i] += Ae[(size_t)e * 64 + c2 * 8 + c8];
             }
-    for (int64_t v = 0; v < nv; ++v)
-        if (vdir[v]) tri.push_back({v, v, -1, 1.0});
-    std::sort(tri.begin(), tri.end(), [](const Tri &a, const Tri &b) {
-        return a.r != b.r ? a.r < b.r : (a.c != b.c ? a.c < b.c : a.e < b.e);
-    });
+        }
+        for (int i = 1; i < k; ++i)  // insertion sort by column
+            for (int j2 = i; j2 > 0 && cols[j2 - 1] > cols[j2]; --j2) {
+                std::swap(cols[j2 - 1], cols[j2]);
+                std::swap(vals[j2 - 1], vals[j2]);
+            }
+        return k;
+    };
     std::vector<int64_t> rp(nv + 1, 0);
-    std::vector<int32_t> ci;
-    std::vector<double> val, dg(nv, 1.0);
-    for (size_t q = 0; q < tri.size();) {
-        size_t q2 = q;
-        double sum = 0.0;
-        while (q2 < tri.size() && tri[q2].r == tri[q].r && tri[q2].c == tri[q].c) sum += tri[q2++].v;
-        ci.push_back((int32_t)tri[q].c);
-        val.push_back(sum);
-        rp[tri[q].r + 1] += 1;
-        if (tri[q].r == tri[q].c) dg[tri[q].r] = sum;
-        q = q2;
-    }
+    semh::parallel_for(nv, [&](int64_t v0, int64_t v1) {
+        std::vector<int32_t> cols((size_t)8 * maxdeg);
+        std::vector<double> vals((size_t)8 * maxdeg);
+        for (int64_t v = v0; v < v1; ++v) rp[v + 1] = row_entries(v, cols.data(), vals.data());
+    }, 1024);
     for (int64_t v = 0; v < nv; ++v) rp[v + 1] += rp[v];
+    std::vector<int32_t> ci((size_t)rp[nv]);
+    std::vector<double> val((size_t)rp[nv]), dg(nv, 1.0);
+    semh::parallel_for(nv, [&](int64_t v0, int64_t v1) {
+        for (int64_t v = v0; v < v1; ++v) {
+            const int k = row_entries(v, ci.data() + rp[v], val.data() + rp[v]);
+            for (int i = 0; i < k; ++i)
+                if (ci[rp[v] + i] == v) dg[v] = val[rp[v] + i];
+        }
+    }, 1024);
     for (double &d : dg) d = (d != 0.0) ? 1.0 / d : 0.0;
     // ELL form, column-major: entry w of row v at w * nv + v; short rows padded with
     // value 0 and the row's own column

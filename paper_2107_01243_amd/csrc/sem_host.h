@@ -27,7 +27,9 @@ struct GsMaps {
     std::vector<int32_t> big_idx;
 };
 
-void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn);
+// fn(lo, hi) over [0, n) split across host threads, each taking at least `grain`
+// items (serial below that).
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn, int64_t grain = 65536);
 void gll_space(int lx, double *xi, double *w, double *D);
 void box_mesh(int nx, int ny, int nz, int lx, double eps, const double *xi, int64_t *glb,
               uint8_t *dir, double *xyz);

@@ -658,6 +658,36 @@ __global__ __launch_bounds__(VT) void k_ccg_update(CoarseArgs A, int it)
     block_partial(rzn, A.partial + ((it + 1) & 1) * g + blockIdx.x, sh);
 }
 
+// Per element, the sums over its points of G_dd / B for d = r, s, t (the local
+// solves' element lengths), in a fixed order: out[e][d].
+__global__ __launch_bounds__(VT) void k_elem_gb(const double *G, const double *B, double *out, int64_t n, int lx3)
+{
+    __shared__ double sh[3][VT / 64];
+    const int64_t e = blockIdx.x;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int p = threadIdx.x; p < lx3; p += VT) {
+        const int64_t t = e * lx3 + p;
+        const double b = B[t];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s[d] += G[d * n + t] / b;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double x = s[d];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) sh[d][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double x = 0.0;
+#pragma unroll
+        for (int q = 0; q < VT / 64; ++q) x += sh[threadIdx.x][q];
+        out[e * 3 + threadIdx.x] = x;
+    }
+}
+
 // Probe vector for the Galerkin coarse matrix: v[e][p] = phi[c][p] in every element.
 __global__ __launch_bounds__(VT) void k_probe(double *v, const double *phi, int c, int64_t nelv, int lx3)
 {
@@ -1532,6 +1562,14 @@ hipError_t sem_launch_coarse_cg(const CoarseArgs *A, int iters, hipStream_t st)
         hipLaunchKernelGGL(k_ccg_spmv, dim3(g), dim3(VT), 0, st, *A, it);
         hipLaunchKernelGGL(k_ccg_update, dim3(g), dim3(VT), 0, st, *A, it);
     }
+    return hipGetLastError();
+}
+hipError_t sem_launch_elem_gb(const double *G, const double *B, double *out, int64_t nelv, int lx3,
+                              hipStream_t st)
+{
+    if (nelv == 0) return hipSuccess;
+    if (nelv > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_elem_gb, dim3((unsigned)nelv), dim3(VT), 0, st, G, B, out, nelv * lx3, lx3);
     return hipGetLastError();
 }
 hipError_t sem_launch_probe(double *v, const double *phi, int c, int64_t nelv, int lx3, hipStream_t st)
