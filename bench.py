@@ -440,6 +440,16 @@ def main():
                                 "frac": round(bpp * P.n / t / 1e9 / HBM_PEAK_GBS, 4)}
                             for k, (t, bpp) in kern.items()}
     out["pcg_fp64_gpoint_iters_per_s"] = round(P.n * out["pcg_fp64_iters"] / out["pcg_fp64_solve_s"] / 1e9, 3)
+    # algorithmic HBM bytes of one FP64 PCG iteration: matvec 11 words per point (r, dinv,
+    # p_old, six G in; p, w out), update 7 words + the owner byte (x, p, r, w, dinv in;
+    # x, r out), gather-scatter 22 B per shared entry (index 4, metadata 2, value in and out)
+    npairs, _, nbe = P.gs.sizes()
+    it_bytes = P.n * (11 * 8 + 7 * 8 + 1) + (2 * npairs + nbe) * 22
+    it_gbs = it_bytes / (out["pcg_fp64_ms_per_iter"] / 1e3) / 1e9
+    out["pcg_fp64_iter_bytes"] = int(it_bytes)
+    out["pcg_fp64_GBs"] = round(it_gbs, 1)
+    out["pcg_fp64_frac_of_peak"] = round(it_gbs / HBM_PEAK_GBS, 4)
+    out["pcg_fp64_frac_of_triad"] = round(it_gbs / beta_triad, 4)
     # the paper's own numbers, on its own hardware (context only)
     out["paper_context"] = {
         "ax_fp64_fraction_of_peak": "more than 10% on most platforms (lx=10, 128-8192 elements)",
