@@ -420,7 +420,7 @@ def test_gmres_to_tolerance(nx, lx, restart):
 
 
 # ------------------------------------------------------------------ two-level Schwarz (Section 4)
-@pytest.mark.parametrize("nx,lx", [(3, 5), (4, 6), (2, 8), (2, 2)])
+@pytest.mark.parametrize("nx,lx", [(3, 5), (4, 6), (2, 8), (2, 2), (3, 4), (3, 8)])
 def test_schwarz_apply_vs_oracle(nx, lx):
     """z = M0^{-1} r on the GPU (fast diagonalisation, Galerkin coarse matrix from probe
     applications, fixed-count coarse CG) against the oracle's dense local solves and
