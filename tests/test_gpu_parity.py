@@ -676,3 +676,35 @@ def test_gradient_helmholtz_grf():
     say(f"   fd={fd:.10e} adj={an:.10e}")
     assert abs(fd - an) <= 1e-6 * abs(an)
     P.coef.set_helmholtz(1.0, 0.0)
+
+
+def test_side_stream_matches_default_stream():
+    """Every call runs on the caller's stream (torch's current stream): the operator, the
+    gather-scatter, PCG (FP64 and mixed) and GMRES with the Schwarz preconditioner on a
+    side stream give bit-identical results to the same calls on the default stream."""
+    say("[side stream]")
+    P = sem.BoxProblem.build(3, 6, 0.05, fp32=True)
+    u = to_dev(workloads.uniform(P.n, workloads.SEED_U))
+    b = P.assemble(to_dev(workloads.uniform(P.n, workloads.SEED_RHS)))
+
+    def run():
+        w = torch.empty_like(u)
+        sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
+        P.gs.op(w)
+        x = torch.zeros_like(b)
+        sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-10)
+        xm = torch.zeros_like(b)
+        sem.pcg_solve(xm, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-10, mixed="reliable")
+        xg = torch.zeros_like(b)
+        sem.gmres_solve(xg, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-10, restart=20, precond="schwarz")
+        return [t.clone() for t in (w, x, xm, xg)]
+
+    ref = run()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        out = run()
+    side.synchronize()
+    for name, r, o in zip(("ax+gs", "pcg", "mixed", "gmres"), ref, out):
+        assert torch.equal(r, o), name
