@@ -140,6 +140,58 @@ def test_ax_full_size_32cubed_lx8_sampled():
     torch.cuda.empty_cache()
 
 
+def test_full_size_32cubed_lx8_gs_fp32_batched_adjoint():
+    """32^3 curved elements, lx = 8, in the benchmark's launch shapes: gs_op over the
+    whole mesh bit-exact against the oracle's gather-scatter; on sampled elements
+    (recomputed by the oracle from its own coordinates and geometry) the FP32 operator
+    (<= 2e-6), the batched three-field Helmholtz operator (h1 = 1/5000, h2 = 2000,
+    <= 1e-12) and the h1-adjoint (<= 1e-12)."""
+    wl = workloads.WORKLOADS["poisson_32x32x32_lx8"]
+    say("[full gs/fp32/batched/adjoint] building 32^3 lx=8")
+    _cache.clear()
+    P = sem.BoxProblem.build(wl.nx, wl.lx, wl.eps, fp32=True)
+    o = oracle.box_mesh(wl.nx, wl.nx, wl.nx, wl.lx, wl.eps)
+    u = workloads.uniform(P.n, workloads.SEED_U)
+    # gather-scatter, whole mesh
+    ug = to_dev(u)
+    P.gs.op(ug)
+    gs_ref = oracle.GS(o["glb"]).op(u)
+    np.testing.assert_array_equal(host(ug), gs_ref)
+    del ug, gs_ref
+    say("   gs bit-exact")
+    xi, wq = oracle.gll(wl.lx)
+    D = oracle.deriv_matrix(xi)
+    npe = wl.lx ** 3
+    rng = np.random.default_rng(11)
+    els = np.concatenate([[0, P.msh.nelv - 1], rng.choice(P.msh.nelv, 126, replace=False)])
+    idx = (els[:, None] * npe + np.arange(npe)[None, :]).reshape(-1)
+    G, B, _ = oracle.geometry(wl.lx, D, wq, o["x"][idx], o["y"][idx], o["z"][idx])
+    del o
+    # FP32 operator
+    w32 = host(P.ax(to_dev(u, torch.float32)))
+    assert rel_inf(w32[idx], oracle.ax_helm(wl.lx, D, G, B, u[idx], 1.0, 0.0)) <= 2e-6
+    del w32
+    # h1-adjoint
+    v = workloads.uniform(P.n, workloads.SEED_RHS)
+    g = host(P.adjoint(to_dev(u), to_dev(v)))
+    assert rel_inf(g[idx], oracle.ax_adjoint(wl.lx, D, G, u[idx], v[idx])) <= 1e-12
+    del g, v
+    say("   fp32 ax and adjoint ok")
+    # batched three fields with a mass term
+    h1, h2 = 1.0 / 5000.0, 2000.0
+    P.coef.set_helmholtz(h1, h2)
+    try:
+        us = [workloads.uniform(P.n, sd) for sd in workloads.SEED_RHS_FIELDS]
+        W = host(P.ax(to_dev(np.concatenate(us)), nfields=3)).reshape(3, -1)
+        for f in range(3):
+            assert rel_inf(W[f][idx], oracle.ax_helm(wl.lx, D, G, B, us[f][idx], h1, h2)) <= 1e-12
+    finally:
+        P.coef.set_helmholtz(1.0, 0.0)
+    say("   batched ok")
+    del P
+    torch.cuda.empty_cache()
+
+
 def test_pcg_full_size_32cubed_lx8():
     """32^3 curved elements, lx = 8, the benchmark workload: FP64 and mixed solves to
     1e-10 on the assembled U[-1,1] load; each true residual recomputed by the oracle's
