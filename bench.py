@@ -123,7 +123,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the multi-GPU path "
-              "is a design, not part of this build.", file=sys.stderr)
+              "is designed but not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
