@@ -834,10 +834,10 @@ __global__ __launch_bounds__(VT) void k_cg_update(CgUpdateArgs<T> A)
 #pragma unroll
         for (int u = 0; u < UV; ++u) {
             const int64_t t = min(t0 + (int64_t)u * VT, A.n - 1);
-            di[u] = A.dinv[t];
+            di[u] = __builtin_nontemporal_load(A.dinv + t);
             xv[u] = __builtin_nontemporal_load(x + t);
-            pv[u] = p[t];
-            rv[u] = r[t];
+            pv[u] = __builtin_nontemporal_load(p + t);
+            rv[u] = __builtin_nontemporal_load(r + t);
             wv[u] = w[t];
             own[u] = A.owner[t];
         }
@@ -855,7 +855,7 @@ __global__ __launch_bounds__(VT) void k_cg_update(CgUpdateArgs<T> A)
                 T ri = rv[u];
                 if (di[u] != T(0)) {
                     ri = fma(-alpha, wv[u], ri);
-                    r[t] = ri;
+                    __builtin_nontemporal_store(ri, r + t);
                 }
                 if (own[u]) {
                     rz += (double)ri * (double)(di[u] * ri);
@@ -871,14 +871,15 @@ __global__ __launch_bounds__(VT) void k_cg_update(CgUpdateArgs<T> A)
             const int64_t t_end = min(A.n, t0 + (int64_t)UV * VT);
 #pragma unroll
             for (int64_t t = t0 + threadIdx.x; t < t_end; t += VT) {
-                const T di = A.dinv[t];
-                // x is touched only here: streamed with non-temporal hints so that the
-                // last-level cache keeps the vectors the next matvec and gs reuse.
-                __builtin_nontemporal_store(fma(alpha, p[t], __builtin_nontemporal_load(x + t)), x + t);
-                T ri = r[t];
+                const T di = __builtin_nontemporal_load(A.dinv + t);
+                // x, p, r and dinv are streamed with non-temporal hints (x is touched
+                // only here; the others are next read a whole iteration later), so that
+                // the last-level cache keeps w and the gather-scatter's index lists.
+                __builtin_nontemporal_store(fma(alpha, __builtin_nontemporal_load(p + t), __builtin_nontemporal_load(x + t)), x + t);
+                T ri = __builtin_nontemporal_load(r + t);
                 if (di != T(0)) {
                     ri = fma(-alpha, w[t], ri);
-                    r[t] = ri;
+                    __builtin_nontemporal_store(ri, r + t);
                 }
                 if (A.owner[t]) {
                     rz += (double)ri * (double)(di * ri);
