@@ -278,6 +278,8 @@ __global__ __launch_bounds__(VT) void k_comb(CombArgs A)
 // Arnoldi pass (see ArnArgs).  Each workgroup streams one contiguous chunk of
 // points; every lane keeps the m basis values of its point in registers, so the
 // combination and the dots of the combined vector need one read of each vector.
+// The basis (tens of vectors, far beyond the last-level cache) is read with
+// non-temporal hints, as in the Gram-Schmidt passes below.
 template <int MV, int MODE>
 __global__ __launch_bounds__(VT) void k_arn(ArnArgs A, int64_t chunk)
 {
@@ -297,7 +299,7 @@ __global__ __launch_bounds__(VT) void k_arn(ArnArgs A, int64_t chunk)
     for (int64_t t = t0 + threadIdx.x; t < t1; t += VT) {
         double v[MV];
 #pragma unroll
-        for (int i = 0; i < MV; ++i) v[i] = (i < m) ? A.V[i * A.ld + t] : 0.0;
+        for (int i = 0; i < MV; ++i) v[i] = (i < m) ? __builtin_nontemporal_load(A.V + i * A.ld + t) : 0.0;
         double y = A.w[t];
         if constexpr (MODE != 0) {
 #pragma unroll
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(VT) void k_dcgs_dots(DcgsArgs A, int64_t chunk)
     for (int64_t t = t0 + threadIdx.x; t < t1; t += VT) {
         double v[MV];
 #pragma unroll
-        for (int i = 0; i < MV; ++i) v[i] = (i < j) ? A.V[i * A.ld + t] : 0.0;
+        for (int i = 0; i < MV; ++i) v[i] = (i < j) ? __builtin_nontemporal_load(A.V + i * A.ld + t) : 0.0;
         const double u = A.u[t], w = A.w[t];
         const bool own = A.owner[t] != 0;
         const double uo = own ? u : 0.0, wo = own ? w : 0.0;
@@ -443,7 +445,7 @@ __global__ __launch_bounds__(VT) void k_dcgs_update(DcgsArgs A, int64_t chunk)
     for (int64_t t = t0 + threadIdx.x; t < t1; t += VT) {
         double v[MV];
 #pragma unroll
-        for (int i = 0; i < MV; ++i) v[i] = (i < j) ? A.V[i * A.ld + t] : 0.0;
+        for (int i = 0; i < MV; ++i) v[i] = (i < j) ? __builtin_nontemporal_load(A.V + i * A.ld + t) : 0.0;
         const double u = A.u[t];
         double q = u, y = A.w[t];
 #pragma unroll
@@ -932,16 +934,17 @@ __global__ __launch_bounds__(VT) void k_cg1_update(Cg1UpdateArgs A)
         const int64_t t_end = min(A.n, (int64_t)(blockIdx.x + 1) * CHUNK);
 #pragma unroll
         for (int64_t t = (int64_t)blockIdx.x * CHUNK + threadIdx.x; t < t_end; t += VT) {
-            const double di = A.dinv[t];
-            double ri = r[t];
-            const double pn = fma(beta, p[t], di * ri);
-            const double sn = fma(beta, s[t], w[t]);
-            p[t] = pn;
-            s[t] = sn;
+            // every vector but w streamed non-temporally, as in the two-reduction update
+            const double di = __builtin_nontemporal_load(A.dinv + t);
+            double ri = __builtin_nontemporal_load(r + t);
+            const double pn = fma(beta, __builtin_nontemporal_load(p + t), di * ri);
+            const double sn = fma(beta, __builtin_nontemporal_load(s + t), w[t]);
+            __builtin_nontemporal_store(pn, p + t);
+            __builtin_nontemporal_store(sn, s + t);
             __builtin_nontemporal_store(fma(alpha, pn, __builtin_nontemporal_load(x + t)), x + t);
             if (di != 0.0) {
                 ri = fma(-alpha, sn, ri);
-                r[t] = ri;
+                __builtin_nontemporal_store(ri, r + t);
             }
             if (A.owner[t]) {
                 rz += ri * (di * ri);
