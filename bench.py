@@ -6,18 +6,27 @@ operand u ~ U[-1,1] (seed 0), load vector U[-1,1] (seed 1) assembled and masked.
 
 One step = the whole hot path once:
   (a) R back-to-back ax_helm launches (the paper's matrix-vector benchmark loop,
-      Listing 2) on u, followed by ten gs_op launches,
+      Listing 2), followed by ten gs_op launches; the launches take their operand and
+      result in turn from four (u, w) pairs, 1.07 GB together, so that no launch finds
+      its operand in the 256 MB last-level cache (HBM-resident inputs, as inside a
+      solver),
   (b) FP64 Jacobi-PCG solves to relative residual 1e-10, in the two-reduction and the
       single-reduction (Chronopoulos-Gear) forms,
   (c) the mixed solves to 1e-10: FP32 Jacobi-PCG with FP64 reliable updates, and
       FP64 flexible CG around an FP32 Jacobi-PCG.
 value = FP64 ax_helm GDOF/s = n_p / (average ax_helm launch time), from HIP events
-on the launch stream over the timed steps.  The JSON line also carries both solve
+on the launch stream over the timed steps.  Also reported: the same kernel with one
+operand reused back to back (warm cache) and with a 1 GiB read before each launch.  The JSON line also carries both solve
 times, iteration counts, the roofline of the ax_helm kernel and the CPU oracle
 baseline.  After the timed steps (not part of ms_per_step) the same load is solved
 with the paper's pressure solver (GMRES(30) with the two-level additive Schwarz
 preconditioner), and a sequence of slowly varying loads is solved with a 20-vector
 projection space (initial guesses from previous solutions); both are reported.
+
+The CPU baseline (rank 0) is the oracle on the host cores: its ax_helm (all threads
+and one thread), its gather-scatter, a 60-iteration PCG sample, and its whole PCG
+solve to the same target, against which the GPU's FP64 and mixed solutions are
+compared (--no-oracle-solve skips that solve).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -66,39 +75,87 @@ def profiled_traffic(kernel):
         return None
 
 
-def cpu_baseline(wl, seconds=15.0):
-    """The oracle's ax_helm on the same 32^3, lx=8 curved mesh, timed on the host."""
-    import oracle
-    import workloads
-
-    t0 = time.time()
-    m = oracle.box_mesh(wl.nx, wl.nx, wl.nx, wl.lx, wl.eps)
-    xi, w = oracle.gll(wl.lx)
-    D = oracle.deriv_matrix(xi)
-    G, B, _ = oracle.geometry(wl.lx, D, w, m["x"], m["y"], m["z"])
-    del m
-    u = workloads.uniform(wl.n_local, workloads.SEED_U)
-    log(f"cpu baseline setup {time.time() - t0:.1f}s")
-    reps, t = 0, 0.0
-    while t < seconds or reps < 2:
-        t1 = time.perf_counter()
-        oracle.ax_helm(wl.lx, D, G, B, u, 1.0, 0.0)
-        t += time.perf_counter() - t1
-        reps += 1
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    cores = min(cores, os.cpu_count() or cores)
-    model = "unknown CPU"
+def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": wl.n_local * reps / t / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} oracle ax_helm applications on the full 32^3 lx=8 curved mesh "
-                      f"({wl.n_local} local points), FP64, {t:.1f}s, {cores} threads of {model} "
-                      f"({os.cpu_count()} logical CPUs visible)"}
+    return "unknown CPU"
+
+
+def _host_threads():
+    n = int(os.environ.get("OMP_NUM_THREADS", 0) or 0)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return min(n, avail) if n > 0 else avail
+
+
+def _timed(fn, seconds, min_reps=2):
+    reps, t = 0, 0.0
+    while t < seconds or reps < min_reps:
+        t1 = time.perf_counter()
+        fn()
+        t += time.perf_counter() - t1
+        reps += 1
+    return t / reps, reps
+
+
+def cpu_baseline(wl, gpu_iters, full_solve=False, mixed=None):
+    """The oracle (plain FP64 C, OpenMP) on the same 32^3, lx=8 curved mesh, timed on the
+    host: ax_helm with all host threads (the reported value) and with one thread, the
+    gather-scatter, and a bounded sample of PCG iterations (the full solve time is that
+    per-iteration time times the iteration count).  With full_solve, the oracle's whole
+    PCG solve to the same target also runs, and the GPU solutions in `mixed` (name ->
+    host array) are compared with it."""
+    import oracle
+    import workloads
+    from paper_2107_01243_amd import RTOL_MARGIN
+
+    threads = _host_threads()
+    oracle.set_threads(threads)
+    t0 = time.time()
+    O = oracle.Problem(wl.nx, wl.lx, wl.eps)
+    u = workloads.uniform(wl.n_local, workloads.SEED_U)
+    log(f"cpu baseline: oracle setup {time.time() - t0:.1f}s ({threads} threads)")
+    t_ax, r_ax = _timed(lambda: O.ax_local(u), 6.0)
+    oracle.set_threads(1)
+    t_ax1, r_ax1 = _timed(lambda: O.ax_local(u), 3.0, min_reps=1)
+    oracle.set_threads(threads)
+    t_gs, r_gs = _timed(lambda: O.gs.op(u), 2.0)
+    bo = O.assemble_rhs(workloads.uniform(wl.n_local, workloads.SEED_RHS))
+    sample_it = 60
+    t1 = time.perf_counter()
+    O.pcg(bo, rtol=0.0, max_iter=sample_it)
+    t_it = (time.perf_counter() - t1) / sample_it
+    log(f"cpu baseline: ax {t_ax:.3f}s ({threads} threads), {t_ax1:.3f}s (1 thread), gs {t_gs:.3f}s, "
+        f"PCG {t_it * 1e3:.1f} ms/iteration")
+    model = _cpu_model()
+    out = {"value": round(wl.n_local / t_ax / 1e9, 4), "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+           "sample": f"oracle ax_helm on the full 32^3 lx=8 curved mesh ({wl.n_local} local points), FP64, "
+                     f"{r_ax} applications with {threads} threads of {model} "
+                     f"({os.cpu_count()} logical CPUs visible); also {r_ax1} application(s) on 1 thread, "
+                     f"{r_gs} gather-scatters and {sample_it} PCG iterations on the same mesh",
+           "ax_gdofs_1_thread": round(wl.n_local / t_ax1 / 1e9, 4),
+           "ax_s": round(t_ax, 4), "ax_s_1_thread": round(t_ax1, 4),
+           "gs_s": round(t_gs, 4),
+           "pcg_ms_per_iter": round(t_it * 1e3, 3),
+           "pcg_solve_s_extrapolated": round(t_it * gpu_iters, 2),
+           "pcg_extrapolation": f"{sample_it}-iteration sample x {gpu_iters} iterations (the GPU FP64 solve's count)"}
+    if full_solve:
+        t1 = time.perf_counter()
+        xo, io = O.pcg(bo, rtol=RTOL_MARGIN * wl.rtol,
+                       progress=lambda it, r: log(f"oracle PCG iteration {it}: {r:.3e}"), every=250)
+        out["pcg_solve_s"] = round(time.perf_counter() - t1, 2)
+        out["pcg_iters"] = io["iters"]
+        xmax = float(np.abs(xo).max())
+        out["solution_err_vs_oracle"] = {k: float(np.abs(v - xo).max() / xmax) for k, v in (mixed or {}).items()}
+        log(f"oracle PCG solve {out['pcg_solve_s']}s, {io['iters']} iterations; errors vs oracle "
+            f"{out['solution_err_vs_oracle']}")
+    return out
 
 
 def main():
@@ -108,6 +165,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--reps", type=int, default=20, help="ax_helm launches per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-solve", action="store_true",
+                    help="CPU baseline without the oracle's full PCG solve (and the solution errors)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-pressure", action="store_true", help="skip the GMRES + Schwarz solve")
     ap.add_argument("--proj-steps", type=int, default=8,
@@ -138,6 +197,11 @@ def main():
     u = torch.from_numpy(workloads.uniform(P.n, workloads.SEED_U)).cuda()
     b = P.assemble(torch.from_numpy(workloads.uniform(P.n, workloads.SEED_RHS)).cuda())
     w = torch.empty_like(u)
+    # ax_helm operands used in turn: each launch's u and w were last touched NROT
+    # launches earlier, beyond the reach of the 256 MB last-level cache
+    NROT = 4
+    us = [u] + [torch.from_numpy(workloads.uniform(P.n, 100 + i)).cuda() for i in range(NROT - 1)]
+    ws = [w] + [torch.empty_like(u) for _ in range(NROT - 1)]
     x = torch.zeros_like(b)
     torch.cuda.synchronize()
     log(f"setup {time.time() - t0:.1f}s, n_local={P.n}")
@@ -168,8 +232,8 @@ def main():
 
     if a.profile:
         sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
-        for _ in range(a.reps):
-            sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
+        for i in range(a.reps):
+            sem.ax_helm(ws[i % NROT], us[i % NROT], P.coef, P.msh, P.Xh)
         P.gs.op(w)
         x.zero_()
         sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=1e-30, max_iter=20, check_every=20,
@@ -213,8 +277,8 @@ def main():
     def step(record):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
-        for _ in range(a.reps):
-            sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
+        for i in range(a.reps):
+            sem.ax_helm(ws[i % NROT], us[i % NROT], P.coef, P.msh, P.Xh)
         ev[1].record(stream)
         for _ in range(10):
             P.gs.op(w)
@@ -301,39 +365,59 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - tb
     cold_s = ax_cold()
-    log(f"ax cold-cache {cold_s * 1e6:.1f} us/launch")
+    log(f"ax with the cache flushed before each launch {cold_s * 1e6:.1f} us/launch")
 
     def t_launch(fn, reps=20):
-        """Average launch time (s) of fn over reps back-to-back launches, HIP events."""
-        fn()
+        """Average launch time (s) of fn(i) over reps back-to-back launches i = 0..reps-1,
+        HIP events on the launch stream."""
+        fn(reps)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(reps):
-            fn()
+        for i in range(reps):
+            fn(i)
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps / 1e3
+
+    warm_s = t_launch(lambda i: sem.ax_helm(w, u, P.coef, P.msh, P.Xh))
+    log(f"ax with one operand reused back to back {warm_s * 1e6:.1f} us/launch")
+
+    # the solutions of each solver once more (untimed), for the comparison with the
+    # oracle's own solve in the CPU baseline
+    sols = {}
+    if not a.no_cpu_baseline and not a.no_oracle_solve:
+        modes = [("fp64", {}), ("fp64_single_reduction", {"single_reduction": True})]
+        if not a.no_mixed:
+            modes += [("mixed_reliable", {"mixed": "reliable", "check_every": 10}),
+                      ("mixed_fcg", {"mixed": "fcg", "inner_rtol": a.inner_rtol, "inner_max_iter": 5000})]
+        for name, kw in modes:
+            kw = {"check_every": 50, **kw}
+            x.zero_()
+            sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, rtol=wl.rtol, **kw)
+            sols[name] = x.cpu().numpy()
 
     # the other kernels of the path on the same mesh, each against its own bytes per
     # point: FP32 ax_helm (8 words), the h1-adjoint (u, v, six G, g: 9 words), and the
     # batched three-field Helmholtz operator (3 u, 3 w, six G, B: 13 words per point
     # for three fields) with h1 = 1/Re, h2 = 1/dt of the velocity solves (Re = 5000,
     # dt = 5e-4), in FP64 and FP32
+    # (operands rotated over NROT sets, as for the FP64 operator)
     kern = {}
-    u32, w32 = u.float(), torch.empty(P.n, dtype=torch.float32, device="cuda")
-    t = t_launch(lambda: sem.ax_helm(w32, u32, P.coef, P.msh, P.Xh))
+    u32 = [v.float() for v in us]
+    w32 = [torch.empty_like(v) for v in u32]
+    t = t_launch(lambda i: sem.ax_helm(w32[i % NROT], u32[i % NROT], P.coef, P.msh, P.Xh))
     kern["ax_f32"] = (t, 8 * 4)
-    g = torch.empty_like(u)
-    t = t_launch(lambda: sem.ax_helm_adjoint(g, u, w, P.coef, P.msh, P.Xh))
+    t = t_launch(lambda i: sem.ax_helm_adjoint(ws[i % NROT], us[i % NROT], us[(i + 1) % NROT], P.coef, P.msh,
+                                               P.Xh))
     kern["adjoint_f64"] = (t, 9 * 8)
-    del g, u32, w32
+    del u32, w32
     P.coef.set_helmholtz(1.0 / 5000.0, 1.0 / 5e-4)
     u3 = torch.from_numpy(np.concatenate([workloads.uniform(P.n, sd) for sd in (0, 5, 6)])).cuda()
     w3 = torch.empty_like(u3)
-    t = t_launch(lambda: sem.ax_helm(w3, u3, P.coef, P.msh, P.Xh, 3))
+    t = t_launch(lambda i: sem.ax_helm(w3, u3, P.coef, P.msh, P.Xh, 3))
     kern["ax_batched3_f64"] = (t, 13 * 8)
     u3, w3 = u3.float(), w3.float()
-    t = t_launch(lambda: sem.ax_helm(w3, u3, P.coef, P.msh, P.Xh, 3))
+    t = t_launch(lambda i: sem.ax_helm(w3, u3, P.coef, P.msh, P.Xh, 3))
     kern["ax_batched3_f32"] = (t, 13 * 4)
     del u3, w3
     P.coef.set_helmholtz(1.0, 0.0)
@@ -400,9 +484,12 @@ def main():
         "config": {"workload": wl.name, "elements": wl.nelv, "lx": wl.lx, "n_local": P.n,
                    "n_unique": wl.n_unique, "deformation": wl.eps, "h1": 1.0, "h2": 0.0,
                    "rtol": wl.rtol, "ax_launches_per_step": a.reps},
-        "ax_us_cold_cache": round(cold_s * 1e6, 2),
-        "ax_gdofs_cold_cache": round(P.n / cold_s / 1e9, 3),
-        "ax_frac_cold_cache": round(AX_WORDS_PER_POINT * 8 * P.n / cold_s / 1e9 / HBM_PEAK_GBS, 4),
+        "ax_operands": f"{NROT} (u, w) pairs used in turn ({NROT * 2 * 8 * P.n / 1e9:.2f} GB, beyond the "
+                       "256 MB last-level cache)",
+        "ax_us_warm_same_operand": round(warm_s * 1e6, 2),
+        "ax_frac_warm_same_operand": round(AX_WORDS_PER_POINT * 8 * P.n / warm_s / 1e9 / HBM_PEAK_GBS, 4),
+        "ax_us_cache_flushed": round(cold_s * 1e6, 2),
+        "ax_frac_cache_flushed": round(AX_WORDS_PER_POINT * 8 * P.n / cold_s / 1e9 / HBM_PEAK_GBS, 4),
         "beta_triad_GBs": round(beta_triad, 1),
         "beta_copy_GBs": round(beta_copy, 1),
         "ax_frac_of_triad_beta": round(achieved / beta_triad, 4),
@@ -479,9 +566,11 @@ def main():
             "proj_speedup_after_4": round(proj_rec[0][0] / float(np.mean([r[0] for r in warm])), 3),
         })
     if not a.no_cpu_baseline:
-        del P, u, w, x, b
+        del P, u, w, x, b, us, ws
         torch.cuda.empty_cache()
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline(wl, out["pcg_fp64_iters"], full_solve=bool(sols), mixed=sols)
+        if sols:
+            out["solution_err_vs_oracle"] = out["cpu_baseline"].pop("solution_err_vs_oracle")
     print(json.dumps(out), flush=True)
 
 

@@ -59,6 +59,15 @@ typedef enum { SEM_F64 = 0, SEM_F32 = 1 } sem_dtype;
 #define SEM_LX_MIN 2
 #define SEM_LX_MAX 16
 
+/* Stopping margin shared by every solver (sem_pcg_solve, sem_gmres_solve,
+ * sem_proj_solve).  A solve asked for a relative tolerance rtol > 0 iterates until
+ * both its recursive residual and its own FP64 evaluation of the true residual meet
+ * |b - A x| <= SEM_RTOL_MARGIN * rtol * |b|.  Another FP64 evaluation of the same
+ * residual (other summation order, FMA or not, geometric factors computed by other
+ * code) differs by rounding of order eps * |A| |x|, which reaches ~15% of 1e-10 on
+ * meshes of 1e8 points; the margin keeps such evaluations at or below rtol. */
+#define SEM_RTOL_MARGIN 0.8
+
 typedef struct sem_space_s *sem_space; /* Xh: lx, GLL points/weights, D (Eq. 7-9)   */
 typedef struct sem_mesh_s *sem_mesh;   /* msh: nelv, lx, global ids, Dirichlet mask  */
 typedef struct sem_coef_s *sem_coef;   /* coef: G, B, h1, h2, Jacobi cache            */
@@ -163,15 +172,20 @@ sem_status sem_ax_helm(void *w, const void *u, sem_coef coef, sem_mesh msh, sem_
 sem_status sem_ax_helm_adjoint(void *g, const void *u, const void *v, sem_coef coef,
                                sem_mesh msh, sem_space Xh, sem_dtype dt, void *stream);
 
-/* Jacobi inverse used by the solver: dinv = 1 / QQ^T(diag A_L), 0 on Dirichlet
- * points (device FP64 output, n_p). */
+/* Jacobi inverse used by the solvers: dinv = 1 / QQ^T(diag A_L), 0 on Dirichlet
+ * points (device FP64 output, n_p, caller-owned).  The preconditioner of the velocity
+ * solves is Jacobi (Section 4); the paper does not define its blocks, and this is
+ * point Jacobi: the exact diagonal of the assembled operator of Eq. 10, including the
+ * G12/G13/G23 cross terms at element boundaries.  The result is also cached in coef
+ * (recomputed after sem_coef_set_helmholtz).  Enqueued on stream. */
 sem_status sem_jacobi_inverse(double *dinv, sem_coef coef, sem_mesh msh, sem_space Xh,
                               sem_gs gs, void *stream);
 
 /* ---------------------------------------------------------------- solver */
 typedef struct {
-    double rtol;        /* stop when |r|/|b| <= rtol (unique-node 2-norms of the
-                           recursive residual); <= 0: run exactly max_iter iterations */
+    double rtol;        /* stop when |r|/|b| <= SEM_RTOL_MARGIN * rtol (unique-node
+                           2-norms) for the recursive residual and for the FP64 true
+                           residual b - A x; <= 0: run exactly max_iter iterations   */
     int max_iter;       /* outer iteration cap (>= 1)                                 */
     int check_every;    /* host polls convergence every this many iterations (>= 1)   */
     int mixed;          /* 0: FP64 Jacobi-PCG.
@@ -206,7 +220,8 @@ typedef struct {
     int iters;          /* FP64: CG iterations; mixed 1: residual replacements;
                            mixed 2: outer flexible-CG iterations                        */
     int inner_iters;    /* mixed: total FP32 CG iterations                             */
-    int converged;      /* 1 when rel_res <= rtol                                      */
+    int converged;      /* 1 when the stopping test was met (sem_proj_solve: when
+                           true_rel_res <= rtol)                                      */
     double rel_res;     /* recursive |r|/|b| at exit                                   */
     double true_rel_res;/* |b - A x|/|b| recomputed in FP64 at exit                    */
 } sem_pcg_info;
@@ -228,7 +243,8 @@ sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef,
  * pass is made in the same passes over the data as the next vector's first), Givens
  * rotations, restart after m steps from the true residual b - A x.  Solves mask QQ^T A_L(h1, h2) x = b for one
  * field (x, b device FP64, b assembled and masked).  Converged when |b - A x| <= rtol |b|
- * for the true residual (checked at every restart and at exit).  Device memory:
+ * for the true residual (checked at every restart and at exit; both the cycle's
+ * least-squares estimate and that check use SEM_RTOL_MARGIN * rtol).  Device memory:
  * (2 m + 2) vectors of n_p values, kept by the coef handle between calls. */
 typedef struct {
     double rtol;      /* > 0, relative to |b|                                          */
@@ -309,6 +325,8 @@ sem_status sem_stream_triad(double *a, const double *b, const double *c, double 
 /* ---------------------------------------------------------------- misc */
 const char *sem_last_error(void);
 const char *sem_version(void);
+/* SEM_RTOL_MARGIN as built into the library. */
+double sem_rtol_margin(void);
 
 #ifdef __cplusplus
 }

@@ -42,6 +42,12 @@ def build(force: bool = True) -> str:
 
 
 _lib = None
+_PROGRESS = C.CFUNCTYPE(None, C.c_int, C.c_double)
+
+
+def set_threads(nthreads: int) -> int:
+    """Host threads of the oracle's parallel loops; returns the previous count."""
+    return lib().orc_set_threads(int(nthreads))
 
 
 def lib():
@@ -91,8 +97,10 @@ def lib():
         L.orc_wdot.restype = C.c_double
         L.orc_pcg.argtypes = [C.c_int64, C.c_int, _f64p, _f64p, vp, vp, C.c_double, vp,
                               C.c_double, vp, vp, _f64p, _f64p, _f64p, C.c_double, C.c_int,
-                              C.POINTER(C.c_int), C.POINTER(C.c_double)]
+                              C.POINTER(C.c_int), C.POINTER(C.c_double), _PROGRESS, C.c_int]
         L.orc_pcg.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -287,16 +295,18 @@ class Problem:
         b[self.dirichlet.astype(bool)] = 0.0
         return b
 
-    def pcg(self, b, x0=None, rtol=1e-10, max_iter=100000):
-        """Jacobi-PCG (Section 4 velocity solver).  rtol <= 0: exactly max_iter steps."""
+    def pcg(self, b, x0=None, rtol=1e-10, max_iter=100000, progress=None, every=100):
+        """Jacobi-PCG (Section 4 velocity solver).  rtol <= 0: exactly max_iter steps.
+        progress(iteration, rel_res), if given, is called every `every` iterations."""
         b = np.ascontiguousarray(b, dtype=np.float64)
         x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
         it = C.c_int(0)
         rr = C.c_double(0.0)
+        cb = _PROGRESS(progress) if progress is not None else _PROGRESS()
         st = lib().orc_pcg(self.nelv, self.lx, self.D, self.G, _ptr(self.B), _ptr(self._h1a),
                            self._h1s, _ptr(self._h2a), self._h2s, self.gs._h,
                            _ptr(self.dirichlet), self.dinv, b, x, float(rtol), int(max_iter),
-                           C.byref(it), C.byref(rr))
+                           C.byref(it), C.byref(rr), cb, int(every))
         return x, dict(status=st, iters=it.value, rel_res=rr.value)
 
     def dot(self, a, b):

@@ -41,6 +41,7 @@
  *    rows and columns of boundary nodes (mask).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -72,6 +73,16 @@ static void legendre(int N, double x, double *LN, double *dLN)
  * Chebyshev-Gauss-Lobatto guesses; w_i = 2 / (N (N+1) L_N(xi_i)^2).
  * Returns 0 on success, -1 for lx outside [2, 32].
  */
+/* Host threads of the parallel loops (timing at a stated core count); returns the
+ * count in effect before the call.  No arithmetic depends on it except the order of
+ * the partial sums of the inner products. */
+EXPORT int orc_set_threads(int nthreads)
+{
+    const int before = omp_get_max_threads();
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return before;
+}
+
 EXPORT int orc_gll(int lx, double *xi, double *w)
 {
     if (lx < 2 || lx > 32) return -1;
@@ -439,6 +450,7 @@ EXPORT void orc_gs_free(orc_gs *gs)
 /* multiplicity of every local point: QQ^T applied to ones */
 EXPORT void orc_multiplicity(const orc_gs *gs, double *mult)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < gs->n; ++p) mult[p] = 1.0;
     orc_gs_op(gs, mult);
 }
@@ -518,6 +530,7 @@ EXPORT void orc_jacobi_dinv(int64_t nelv, int lx, const double *D, const double 
     const int64_t n = nelv * (int64_t)lx * lx * lx;
     orc_diag(nelv, lx, D, G, B, h1, h1s, h2, h2s, dinv);
     orc_gs_op(gs, dinv);
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < n; ++p)
         dinv[p] = (dirichlet && dirichlet[p]) ? 0.0 : 1.0 / dinv[p];
 }
@@ -544,15 +557,18 @@ EXPORT double orc_wdot(int64_t n, const double *a, const double *b, const double
  *           stop if |r|/|b| <= rtol; z = dinv r; beta = (r,z)_new/(r,z)_old;
  *           p = z + beta p.
  * Norms and dots are the 1/mult-weighted products.  rtol <= 0 runs exactly
- * max_iter iterations.  x holds the initial guess on entry.
+ * max_iter iterations.  x holds the initial guess on entry.  progress (may be NULL)
+ * is called with the iteration count and |r|/|b| every `every` iterations.
  * Returns 0 converged (or fixed count done), 1 not converged, 2 breakdown.
  */
+typedef void (*orc_progress_fn)(int iteration, double rel_res);
+
 EXPORT int orc_pcg(int64_t nelv, int lx, const double *D, const double *G,
                    const double *B, const double *h1, double h1s,
                    const double *h2, double h2s, const orc_gs *gs,
                    const uint8_t *dirichlet, const double *dinv,
                    const double *b, double *x, double rtol, int max_iter,
-                   int *iters_out, double *relres_out)
+                   int *iters_out, double *relres_out, orc_progress_fn progress, int every)
 {
     const int64_t n = nelv * (int64_t)lx * lx * lx;
     double *mult = malloc(sizeof(double) * n);
@@ -563,8 +579,11 @@ EXPORT int orc_pcg(int64_t nelv, int lx, const double *D, const double *G,
     orc_multiplicity(gs, mult);
 
     orc_apply(nelv, lx, D, G, B, h1, h1s, h2, h2s, gs, dirichlet, x, w);
+#pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n; ++q) r[q] = b[q] - w[q];
+#pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n; ++q) z[q] = dinv[q] * r[q];
+#pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n; ++q) p[q] = z[q];
     const double bnorm = sqrt(wdot(n, b, b, mult));
     double rz = wdot(n, r, z, mult);
@@ -576,16 +595,21 @@ EXPORT int orc_pcg(int64_t nelv, int lx, const double *D, const double *G,
         const double pw = wdot(n, p, w, mult);
         if (!(pw > 0.0) || !isfinite(rz)) { status = 2; break; }
         const double alpha = rz / pw;
+#pragma omp parallel for schedule(static)
         for (int64_t q = 0; q < n; ++q) x[q] += alpha * p[q];
+#pragma omp parallel for schedule(static)
         for (int64_t q = 0; q < n; ++q) r[q] -= alpha * w[q];
         it += 1;
         rel = sqrt(wdot(n, r, r, mult)) / bnorm;
+        if (progress && every > 0 && it % every == 0) progress(it, rel);
         if (rtol > 0 && rel <= rtol) { status = 0; break; }
+#pragma omp parallel for schedule(static)
         for (int64_t q = 0; q < n; ++q) z[q] = dinv[q] * r[q];
         const double rz_new = wdot(n, r, z, mult);
         if (rz_new == 0.0) { status = 0; break; }
         const double beta = rz_new / rz;
         rz = rz_new;
+#pragma omp parallel for schedule(static)
         for (int64_t q = 0; q < n; ++q) p[q] = z[q] + beta * p[q];
     }
     if (status == 1 && rtol <= 0 && it == max_iter) status = 0;

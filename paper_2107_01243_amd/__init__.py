@@ -7,11 +7,12 @@ Schwarz preconditioning (the pressure solver of Section 4),
 projection onto previous solutions (Section 4, Table 2), and the h1-adjoint behind
 torch.autograd.
 """
-from .sem import (BoxProblem, Coef, GS, GmresParams, Mesh, PcgInfo, PcgParams, Projection, SemError, Space,
+from .sem import (RTOL_MARGIN, BoxProblem, Coef, GS, GmresParams, Mesh, PcgInfo, PcgParams, Projection, SemError,
+                  Space,
                   ax_helm, ax_helm_adjoint, box_mesh, gmres_solve, jacobi_inverse, lib, mask, pcg_solve,
                   schwarz_apply, stream_triad)
 from .autograd import HelmholtzSolve
 
-__all__ = ["BoxProblem", "Coef", "GS", "GmresParams", "Mesh", "PcgInfo", "PcgParams", "Projection", "SemError",
+__all__ = ["RTOL_MARGIN", "BoxProblem", "Coef", "GS", "GmresParams", "Mesh", "PcgInfo", "PcgParams", "Projection", "SemError",
            "Space", "ax_helm", "ax_helm_adjoint", "box_mesh", "gmres_solve", "jacobi_inverse", "lib", "mask",
            "pcg_solve", "schwarz_apply", "stream_triad", "HelmholtzSolve"]

@@ -87,6 +87,7 @@ _SIGS = {
     "sem_proj_destroy": ([_vp], None),
     "sem_last_error": ([], C.c_char_p),
     "sem_version": ([], C.c_char_p),
+    "sem_rtol_margin": ([], C.c_double),
 }
 
 
@@ -102,6 +103,10 @@ def _load():
 
 
 _L = _load()
+
+# Every solver iterates to RTOL_MARGIN * rtol by its own FP64 true residual
+# (SEM_RTOL_MARGIN of sem.h), so other FP64 evaluations of it also meet rtol.
+RTOL_MARGIN = float(_L.sem_rtol_margin())
 
 
 def lib():
@@ -270,7 +275,13 @@ class Coef:
         s1 = 0.0 if h1p is not None else float(h1)
         s2 = 0.0 if h2p is not None else float(h2)
         _check(_L.sem_coef_set_helmholtz(self._h, h1p, s1, h2p, s2, _stream(stream)))
-        self.h1, self.h2 = h1, h2
+        # own copies, so that helmholtz() can restore exactly what the handle holds
+        self.h1 = h1.detach().clone() if isinstance(h1, torch.Tensor) else s1
+        self.h2 = h2.detach().clone() if isinstance(h2, torch.Tensor) else s2
+
+    def helmholtz(self):
+        """(h1, h2) as the handle holds them: floats, or FP64 device tensors (copies)."""
+        return self.h1, self.h2
 
     def export(self, stream=None):
         n = self.msh.n
@@ -467,6 +478,15 @@ class BoxProblem:
     @property
     def n(self):
         return self.msh.n
+
+    @property
+    def mult(self):
+        """Multiplicity of every local point (FP64 device tensor, cached)."""
+        m = getattr(self, "_mult", None)
+        if m is None:
+            m = torch.from_numpy(self.gs.maps()[3].astype(np.float64)).to("cuda")
+            self._mult = m
+        return m
 
     @classmethod
     def build(cls, nx: int, lx: int, eps: float = 0.05, fp32: bool = False, ny=None, nz=None):

@@ -5,6 +5,11 @@ the same workload parameters; only the seeded random inputs are shared.
 Tolerances: gather-scatter and maps bit-exact; FP64 arithmetic
 |w - w_ref|_inf / |w_ref|_inf <= 1e-12; FP32 operator vs FP64 oracle <= 2e-6;
 solves as stated per test.
+
+Solves: every libsem solver stops once its own FP64 true residual is at most
+RTOL_MARGIN * rtol, so its iterations are compared with the oracle's textbook PCG
+(or GMRES) run to that same target, and the oracle's own recomputation of the true
+residual of the returned solution must be <= 1.05 * rtol.
 """
 import math
 import os
@@ -25,6 +30,7 @@ from paper_2107_01243_amd import sem  # noqa: E402
 from paper_2107_01243_amd import HelmholtzSolve  # noqa: E402
 
 DEV = "cuda"
+MARGIN = sem.RTOL_MARGIN
 
 
 def say(*a):
@@ -192,10 +198,15 @@ def test_full_size_32cubed_lx8_gs_fp32_batched_adjoint():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.timeout(500)
 def test_pcg_full_size_32cubed_lx8():
-    """32^3 curved elements, lx = 8, the benchmark workload: FP64 and mixed solves to
-    1e-10 on the assembled U[-1,1] load; each true residual recomputed by the oracle's
-    own operator (its own mesh, geometry and gather-scatter) must be <= 1.05e-10."""
+    """32^3 curved elements, lx = 8, the benchmark workload: FP64 solves (two-reduction
+    and single-reduction forms) and both mixed solves to 1e-10 on the assembled
+    U[-1,1] load, against the oracle's own textbook PCG on its own mesh, geometry and
+    gather-scatter: FP64 solutions within 1e-8 (inf-norm, relative) with iteration
+    counts within max(2, 1%); every true residual recomputed by the oracle's operator
+    <= 1.05e-10; the mixed solutions' distance from the oracle's FP64 solution stated
+    and bounded by what two 1e-10 residuals allow."""
     wl = workloads.WORKLOADS["poisson_32x32x32_lx8"]
     say("[pcg full] building 32^3 lx=8")
     _cache.clear()
@@ -211,18 +222,30 @@ def test_pcg_full_size_32cubed_lx8():
     torch.cuda.empty_cache()
     say(f"   fp64 {i64[0]['iters']} it, single reduction {i1[0]['iters']} it, reliable {im[0]['iters']} "
         f"replacements / {im[0]['inner_iters']} it, fcg {iff[0]['iters']} outer / {iff[0]['inner_iters']} inner")
-    assert abs(i1[0]["iters"] - i64[0]["iters"]) <= max(2, math.ceil(0.01 * i64[0]["iters"]))
-    O = oracle.Problem(wl.nx, wl.lx, wl.eps)
+    O = oracle.Problem(wl.nx, wl.lx, wl.eps, progress=say)
     bo = O.assemble_rhs(bl)
     for X, info in ((X64, i64[0]), (X1, i1[0]), (XM, im[0]), (XF, iff[0])):
         tr = O.true_rel_res(X, bo)
         assert tr <= 1.05e-10, tr
         assert abs(info["true_rel_res"] - tr) <= 1e-2 * tr + 1e-13
-    # both solutions meet the same residual bound; their difference is bounded by
-    # kappa * 2e-10 (kappa ~ 1e4-1e5 for Jacobi-preconditioned Poisson at this size)
-    assert rel_inf(X1, X64) <= 1e-5
-    assert rel_inf(XM, X64) <= 1e-5
-    assert rel_inf(XF, X64) <= 1e-5
+    say("   oracle PCG to the same target (textbook form, FP64, host threads)")
+    xo, io = O.pcg(bo, rtol=MARGIN * wl.rtol, progress=lambda it, r: say(f"      oracle it {it}: {r:.3e}"),
+                   every=250)
+    assert io["status"] == 0
+    tol_it = max(2, math.ceil(0.01 * io["iters"]))
+    errs = {name: rel_inf(X, xo) for name, X in (("fp64", X64), ("single_reduction", X1),
+                                                 ("mixed_reliable", XM), ("mixed_fcg", XF))}
+    say(f"   oracle {io['iters']} it; |x - x_oracle|_inf / |x_oracle|_inf: "
+        + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert abs(i64[0]["iters"] - io["iters"]) <= tol_it, (i64[0]["iters"], io["iters"])
+    assert abs(i1[0]["iters"] - io["iters"]) <= tol_it, (i1[0]["iters"], io["iters"])
+    assert errs["fp64"] <= 1e-8
+    assert errs["single_reduction"] <= 1e-8
+    # the mixed solutions meet the same residual bound by another path; their distance
+    # from the oracle's solution is bounded by kappa * 2e-10 (kappa ~ 1e4-1e5 for
+    # Jacobi-preconditioned Poisson at this size)
+    assert errs["mixed_reliable"] <= 1e-5
+    assert errs["mixed_fcg"] <= 1e-5
     assert np.abs(X64[O.dirichlet == 1]).max() == 0.0
 
 
@@ -301,7 +324,7 @@ def test_pcg_to_tolerance(nx, lx, h2):
     bo = O.assemble_rhs(bl)
     b = P.assemble(to_dev(bl))
     np.testing.assert_array_equal(host(b), bo)
-    xo, io = O.pcg(bo, rtol=1e-10)
+    xo, io = O.pcg(bo, rtol=MARGIN * 1e-10)
     x, info = P.solve(b, rtol=1e-10, check_every=20)
     it, ito = info[0]["iters"], io["iters"]
     assert abs(it - ito) <= max(2, math.ceil(0.01 * ito)), (it, ito)
@@ -323,7 +346,7 @@ def test_pcg_three_fields_and_initial_guess():
     x, info = P.solve(b, nfields=3, rtol=1e-10)
     X = host(x).reshape(3, -1)
     for f in range(3):
-        xo, io = O.pcg(O.assemble_rhs(bls[f]), rtol=1e-10)
+        xo, io = O.pcg(O.assemble_rhs(bls[f]), rtol=MARGIN * 1e-10)
         assert abs(info[f]["iters"] - io["iters"]) <= 2
         assert rel_inf(X[f], xo) <= 1e-8
     # restart from the converged solution: zero iterations
@@ -369,7 +392,7 @@ def test_single_reduction_to_tolerance(nx, lx, h2, nf):
     X = host(x).reshape(nf, -1)
     for f in range(nf):
         bo = O.assemble_rhs(bls[f])
-        xo, io = O.pcg(bo, rtol=1e-10)
+        xo, io = O.pcg(bo, rtol=MARGIN * 1e-10)
         it, ito = info[f]["iters"], io["iters"]
         assert abs(it - ito) <= max(2, math.ceil(0.01 * ito)), (it, ito)
         assert rel_inf(X[f], xo) <= 1e-8
@@ -458,7 +481,7 @@ def test_gmres_to_tolerance(nx, lx, restart):
     bl = workloads.uniform(P.n, workloads.SEED_RHS)
     bo = O.assemble_rhs(bl)
     b = P.assemble(to_dev(bl))
-    xo, io = O.gmres(bo, rtol=1e-10, restart=restart)
+    xo, io = O.gmres(bo, rtol=MARGIN * 1e-10, restart=restart)
     x, info = P.gmres(b, rtol=1e-10, restart=restart)
     say(f"   steps {info['iters']} (oracle {io['iters']}), cycles {info['inner_iters']}")
     assert abs(info["iters"] - io["iters"]) <= max(2, math.ceil(0.02 * io["iters"]))
@@ -509,7 +532,7 @@ def test_gmres_schwarz_vs_oracle():
     bl = workloads.uniform(P.n, workloads.SEED_RHS)
     bo = O.assemble_rhs(bl)
     b = P.assemble(to_dev(bl))
-    xo, io = O.gmres(bo, rtol=1e-10, restart=30, precond="schwarz")
+    xo, io = O.gmres(bo, rtol=MARGIN * 1e-10, restart=30, precond="schwarz")
     x, info = P.gmres(b, rtol=1e-10, restart=30, precond="schwarz")
     say(f"   steps {info['iters']} (oracle {io['iters']}), jacobi-PCG would need "
         f"{O.pcg(bo, rtol=1e-10)[1]['iters']}")
@@ -550,7 +573,7 @@ def test_projection_sequence_vs_oracle():
             assert not host(x0).any()
         assert np.abs(host(r) - ro).max() <= 1e-8 * np.abs(bo).max()
         x, info = proj.solve(b, rtol=1e-12)
-        xo, io = O.pcg(bo, x0=x0o, rtol=1e-12)
+        xo, io = O.pcg(bo, x0=x0o, rtol=MARGIN * 1e-12)
         say(f"   step {k}: space {len(L)}, iterations {info['iters']} (oracle {io['iters']}), "
             f"size {proj.size()}")
         assert abs(info["iters"] - io["iters"]) <= max(2, math.ceil(0.01 * io["iters"]))
@@ -613,7 +636,7 @@ def test_projection_full_size_32cubed_lx8():
         xh = host(x)
         tr = O.true_rel_res(xh, O.assemble_rhs(fl))
         say(f"   step {k}: iterations {info['iters']}, oracle true residual {tr:.3e}")
-        assert tr <= 1.2e-10
+        assert tr <= 1.05e-10
         xs.append(xh)
         its.append(info["iters"])
     assert its[2] <= 0.7 * its[0] and its[3] <= 0.7 * its[0], its
@@ -728,6 +751,60 @@ def test_gradient_helmholtz_grf():
     say(f"   fd={fd:.10e} adj={an:.10e}")
     assert abs(fd - an) <= 1e-6 * abs(an)
     P.coef.set_helmholtz(1.0, 0.0)
+
+
+def test_helmholtz_solve_interleaved_and_grad_b():
+    """Two differentiable solves with different h1 on one problem, both forwards before
+    both backwards: each gradient equals the one computed alone (bit for bit), the
+    handle's own coefficients are restored after every call, and dL/db = lambda / mult
+    matches the oracle's adjoint solution and central differences along an assembled
+    direction (the loss is quadratic in b)."""
+    say("[autograd interleaved, dL/db]")
+    P, O = pair(3, 6)
+    P.coef.set_helmholtz(2.0, 5.0)
+    O.set_coef(2.0, 5.0)
+    hA = to_dev(np.exp(0.3 * workloads.uniform(P.n, 21)))
+    hB = to_dev(np.exp(0.3 * workloads.uniform(P.n, 22)))
+    b = P.assemble(to_dev(workloads.uniform(P.n, workloads.SEED_RHS)))
+    ut = P.assemble(to_dev(workloads.uniform(P.n, 23))) * 1e-3
+    mult = P.mult
+
+    def loss(h, bb):
+        u = HelmholtzSolve.apply(h, bb, P, 7.0, 1e-13)
+        return 0.5 * torch.sum((u - ut) ** 2 / mult)
+
+    def alone(h):
+        hv, bv = h.clone().requires_grad_(True), b.clone().requires_grad_(True)
+        loss(hv, bv).backward()
+        return hv.grad.clone(), bv.grad.clone()
+
+    gA, gbA = alone(hA)
+    gB, _ = alone(hB)
+    assert P.coef.helmholtz() == (2.0, 5.0)
+    ha, hb = hA.clone().requires_grad_(True), hB.clone().requires_grad_(True)
+    ba = b.clone().requires_grad_(True)
+    La, Lb = loss(ha, ba), loss(hb, b)
+    Lb.backward()
+    La.backward()
+    assert torch.equal(ha.grad, gA) and torch.equal(hb.grad, gB) and torch.equal(ba.grad, gbA)
+    assert P.coef.helmholtz() == (2.0, 5.0)
+    # the handle's own operator is untouched: a plain solve equals the oracle's
+    x, info = P.solve(b, rtol=1e-10)
+    assert rel_inf(host(x), O.pcg(host(b), rtol=MARGIN * 1e-10)[0]) <= 1e-8
+    # dL/db: lambda / mult with lambda the oracle's adjoint solution
+    O.set_coef(host(hA), 7.0)
+    uo, _ = O.pcg(host(b), rtol=MARGIN * 1e-13)
+    lam, _ = O.pcg(np.where(O.dirichlet == 1, 0.0, uo - host(ut)), rtol=MARGIN * 1e-13)
+    assert rel_inf(host(gbA), lam / O.mult) <= 1e-8
+    db = P.assemble(to_dev(workloads.uniform(P.n, 24)))
+    eps = 1e-3
+    with torch.no_grad():
+        fd = (float(loss(hA, b + eps * db)) - float(loss(hA, b - eps * db))) / (2 * eps)
+    an = float(torch.dot(gbA, db))
+    say(f"   dL/db: fd {fd:.10e} adjoint {an:.10e}")
+    assert abs(fd - an) <= 1e-6 * abs(an)
+    P.coef.set_helmholtz(1.0, 0.0)
+    O.set_coef(1.0, 0.0)
 
 
 def test_side_stream_matches_default_stream():

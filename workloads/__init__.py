@@ -60,8 +60,10 @@ WORKLOADS = {
         "poisson_32x32x32_lx8", 32, 8, 0.05, "one", 0.0, "uniform", 1e-10,
         note="32^3 curved elements, N=7, 16.8M local points; FP64 and mixed solves to 1e-10"),
     "helmholtz_grf_16x16x16_lx8": Workload(
-        "helmholtz_grf_16x16x16_lx8", 16, 8, 0.05, "grf", 1000.0, "sine", 1e-13,
-        note="variable h1 = exp(GRF), h2 = 1/dt, dt = 1e-3; adjoint gradient vs FD"),
+        "helmholtz_grf_16x16x16_lx8", 16, 8, 0.05, "grf", 1000.0, "sine", 1e-12,
+        note="variable h1 = exp(GRF), h2 = 1/dt, dt = 1e-3; adjoint gradient vs FD; forward and adjoint "
+             "solves to 1e-12, the tightest tolerance an FP64 true residual certifies on this mesh and load "
+             "(its rounding floor is ~2e-13)"),
     "poisson_64x64x64_lx8_mixed": Workload(
         "poisson_64x64x64_lx8_mixed", 64, 8, 0.05, "one", 0.0, "sine", 1e-10, mixed=True,
         note="64^3 curved elements, 134M local points; FP32 operator inside FP64 flexible CG"),
@@ -97,13 +99,21 @@ class GRF:
     sigma: float = 0.5
 
     def __call__(self, x, y, z):
+        """Field values at the points (x, y, z) (numpy arrays of one shape), FP64.
+        Evaluated with torch CPU tensors in chunks of points (all host threads)."""
+        import torch
+
         x = np.asarray(x, np.float64)
-        out = np.zeros_like(x)
+        pts = torch.from_numpy(np.stack([x.reshape(-1), np.asarray(y, np.float64).reshape(-1),
+                                         np.asarray(z, np.float64).reshape(-1)], axis=1))
+        om = torch.from_numpy(np.ascontiguousarray(self.omega.T))      # (3, M)
+        ph = torch.from_numpy(self.phi)                                # (M,)
+        out = torch.empty(pts.shape[0], dtype=torch.float64)
+        chunk = 1 << 15
+        for a in range(0, pts.shape[0], chunk):
+            out[a:a + chunk] = torch.cos(torch.addmm(ph, pts[a:a + chunk], om)).sum(dim=1)
         amp = self.sigma * math.sqrt(2.0 / len(self.phi))
-        for m in range(len(self.phi)):
-            o = self.omega[m]
-            out += np.cos(o[0] * x + o[1] * y + o[2] * np.asarray(z) + self.phi[m])
-        return amp * out
+        return (amp * out.numpy()).reshape(x.shape)
 
 
 def grf(seed: int, sigma: float = 0.5, ell: float = 0.2, M: int = 512) -> GRF:
