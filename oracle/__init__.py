@@ -23,7 +23,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sem_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# SEM_ORACLE_LIB: another build of sem_oracle.c to load instead (the sanitizer test
+# loads one built with AddressSanitizer and UndefinedBehaviorSanitizer).
+_LIB_OVERRIDE = os.environ.get("SEM_ORACLE_LIB")
+_BUILT = os.path.join(_HERE, "liboracle.so")
+_LIB = _LIB_OVERRIDE or _BUILT
 
 _i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
@@ -32,13 +36,13 @@ _u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
 
 def build(force: bool = True) -> str:
     """Compile sem_oracle.c into liboracle.so with gcc (FP64, no FP contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+    if force or not os.path.exists(_BUILT) or os.path.getmtime(_BUILT) < os.path.getmtime(_SRC):
+        tmp = _BUILT + ".tmp"
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
                "-shared", "-std=c11", "-D_GNU_SOURCE", "-Wall", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, _BUILT)
+    return _BUILT
 
 
 _lib = None
@@ -53,7 +57,7 @@ def set_threads(nthreads: int) -> int:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not _LIB_OVERRIDE and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build(force=True)
         L = C.CDLL(_LIB)
         vp = C.c_void_p
