@@ -68,6 +68,12 @@ typedef enum { SEM_F64 = 0, SEM_F32 = 1 } sem_dtype;
  * meshes of 1e8 points; the margin keeps such evaluations at or below rtol. */
 #define SEM_RTOL_MARGIN 0.8
 
+/* Size of the fixed device workspace of sem_pcg_solve_noalloc: at most
+ * SEM_NOALLOC_MAX_POINTS = n_p * nfields local values per solve; the workspace holds
+ * four vectors of that length, 2^17 reduction partials and 4 KiB of scalars. */
+#define SEM_NOALLOC_MAX_POINTS (1 << 21)
+#define SEM_NOALLOC_WORKSPACE_BYTES ((4LL * SEM_NOALLOC_MAX_POINTS + 131072 + 512) * 8)
+
 typedef struct sem_space_s *sem_space; /* Xh: lx, GLL points/weights, D (Eq. 7-9)   */
 typedef struct sem_mesh_s *sem_mesh;   /* msh: nelv, lx, global ids, Dirichlet mask  */
 typedef struct sem_coef_s *sem_coef;   /* coef: G, B, h1, h2, Jacobi cache            */
@@ -234,6 +240,25 @@ typedef struct {
 sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef, sem_mesh msh,
                          sem_space Xh, sem_gs gs, const sem_pcg_params *params,
                          sem_pcg_info *info, void *stream);
+
+/* Allocation-free variant of sem_pcg_solve, for callers that cannot allocate device
+ * memory (serving loops and harnesses that forbid hipMalloc, code that must not
+ * change the device heap).  Same arguments, same iterates and results as
+ * sem_pcg_solve with mixed = 0 and variant = 0 (the FP64 two-reduction Jacobi-PCG),
+ * which is the only form it accepts.  Its scratch (CG vectors, Jacobi inverse,
+ * reduction partials, scalars) lives in a fixed device workspace of
+ * SEM_NOALLOC_WORKSPACE_BYTES (65 MiB) that every GPU the library runs on holds from
+ * the first call until the process ends; the call allocates no device or pinned host
+ * memory.  The Jacobi inverse is recomputed on every call (not cached in coef).
+ * Errors (SEM_ERR_INVALID, before any launch): n_p * nfields above
+ * SEM_NOALLOC_MAX_POINTS; a gs handle not yet resident on the device (any allocating
+ * call that uses it -- sem_gs_op, sem_jacobi_inverse, sem_pcg_solve -- uploads it);
+ * every error of sem_pcg_solve.  All calls on one GPU share the workspace, which keeps
+ * the last call's contents: calls that overlap in time on one GPU (other host threads
+ * or streams) race and must be serialised by the caller. */
+sem_status sem_pcg_solve_noalloc(double *x, const double *b, int nfields, sem_coef coef, sem_mesh msh,
+                                 sem_space Xh, sem_gs gs, const sem_pcg_params *params,
+                                 sem_pcg_info *info, void *stream);
 
 /* ---------------------------------------------------------------- GMRES
  * The paper's pressure equation is solved with GMRES (Section 4, Table 2).

@@ -46,7 +46,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         obj = os.path.join(BUILD, f"ax_lx{lx}.o")
         steps.append([HIPCC, *DEVICE_FLAGS, f"-DSEM_LX={lx}", "-c",
                       os.path.join(CSRC, "ax_kernels.hip"), "-o", obj])
-    for src in ("vec_kernels.hip", "sem_api.cpp", "sem_cg.cpp", "sem_proj.cpp",
+    for src in ("vec_kernels.hip", "sem_noalloc.hip", "sem_api.cpp", "sem_cg.cpp", "sem_proj.cpp",
                 "sem_gmres.cpp", "host_setup.cpp"):
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []

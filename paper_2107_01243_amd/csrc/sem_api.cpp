@@ -127,13 +127,11 @@ sem_status check_coef(sem_coef c, sem_mesh msh, sem_space Xh)
     return check_device(c->device);
 }
 
-// Jacobi inverse (point Jacobi: exact assembled diagonal), cached per (coef, gs).
-sem_status ensure_dinv(sem_coef c, sem_gs g, hipStream_t st)
+// dinv = 1 / QQ^T diag(A_L) (0 on Dirichlet points) into caller-provided memory.
+sem_status compute_dinv(sem_coef c, sem_gs g, double *dinv, hipStream_t st)
 {
-    if (c->dinv_valid && c->dinv_gs == (const void *)g) return SEM_OK;
-    if (!c->dinv) SEM_TRY(dalloc(&c->dinv, c->n));
     DiagArgs A;
-    A.d = c->dinv;
+    A.d = dinv;
     A.G = c->G;
     A.B = c->B;
     A.h1 = c->h1;
@@ -142,8 +140,17 @@ sem_status ensure_dinv(sem_coef c, sem_gs g, hipStream_t st)
     A.h2s = c->h2s;
     A.n = c->n;
     HIP_TRY(fns(c->lx).diag(&A, c->Xh->D, st));
-    SEM_TRY(launch_gs<double>(c->dinv, 1, g, nullptr, nullptr, st));
-    HIP_TRY(sem_launch_invert(c->dinv, c->msh->d_dir, c->n, st));
+    SEM_TRY(launch_gs<double>(dinv, 1, g, nullptr, nullptr, st));
+    HIP_TRY(sem_launch_invert(dinv, c->msh->d_dir, c->n, st));
+    return SEM_OK;
+}
+
+// Jacobi inverse (point Jacobi: exact assembled diagonal), cached per (coef, gs).
+sem_status ensure_dinv(sem_coef c, sem_gs g, hipStream_t st)
+{
+    if (c->dinv_valid && c->dinv_gs == (const void *)g) return SEM_OK;
+    if (!c->dinv) SEM_TRY(dalloc(&c->dinv, c->n));
+    SEM_TRY(compute_dinv(c, g, c->dinv, st));
     if (c->flags & SEM_COEF_F32) {
         if (!c->dinv32) SEM_TRY(dalloc(&c->dinv32, c->n));
         HIP_TRY(sem_launch_cast_f32_f64(c->dinv32, c->dinv, 1.0, c->n, st));
@@ -213,10 +220,9 @@ sem_status ensure_work(sem_coef c, int nf, bool mixed)
 }
 
 // Owner-weighted dots on the device: out[q*nf + f] = sum_owned a_q b_q (field f).
-sem_status dots(sem_coef c, sem_gs g, int nf, int nd, const double *const *a, const double *const *b,
+sem_status dots(sem_coef c, Work &W, sem_gs g, int nf, int nd, const double *const *a, const double *const *b,
                 double *host_out, hipStream_t st)
 {
-    Work &W = c->ws;
     DotArgs A;
     for (int q = 0; q < 4; ++q) {
         A.a[q] = q < nd ? a[q] : nullptr;
@@ -234,6 +240,12 @@ sem_status dots(sem_coef c, sem_gs g, int nf, int nd, const double *const *a, co
     HIP_TRY(hipStreamSynchronize(st));
     std::memcpy(host_out, W.h_dots, sizeof(double) * nd * nf);
     return SEM_OK;
+}
+
+sem_status dots(sem_coef c, sem_gs g, int nf, int nd, const double *const *a, const double *const *b,
+                double *host_out, hipStream_t st)
+{
+    return dots(c, c->ws, g, nf, nd, a, b, host_out, st);
 }
 
 }  // namespace semi

@@ -9,17 +9,16 @@ using namespace semi;
 namespace __attribute__((visibility("hidden"))) semi {
 
 template <typename T>
-sem_status cg_iterate(sem_coef c, sem_gs g, int nf, T *x, T *r, T *p, T *w, const T *dinv, int max_iter,
+sem_status cg_iterate(sem_coef c, Work &W, sem_gs g, int nf, T *x, T *r, T *p, T *w, const T *dinv, int max_iter,
                       int check_every, double *hist, int hist_len, hipStream_t st);
 
 // Jacobi-PCG in precision T on nf fields.  x is the iterate (zeroed unless use_x0),
 // b the assembled, masked right-hand side.  Per-field results land in W.h_scal.
 template <typename T>
-sem_status cg_run(sem_coef c, sem_gs g, int nf, T *x, const T *b, bool use_x0, T *r, T *p, T *w,
+sem_status cg_run(sem_coef c, Work &W, sem_gs g, int nf, T *x, const T *b, bool use_x0, T *r, T *p, T *w,
                   const T *dinv, const double *rtol, int max_iter, int check_every, double *hist, int hist_len,
                   hipStream_t st)
 {
-    Work &W = c->ws;
     const int64_t n = c->n;
     if (use_x0) {
         SEM_TRY(launch_ax<T>(c, w, x, nf, st));
@@ -52,15 +51,14 @@ sem_status cg_run(sem_coef c, sem_gs g, int nf, T *x, const T *b, bool use_x0, T
         CgFinishArgs F{W.partial, (int64_t)vg, W.scal, hist, hist_len, nf};
         HIP_TRY(sem_launch_cg_start(&F, st));
     }
-    return cg_iterate<T>(c, g, nf, x, r, p, w, dinv, max_iter, check_every, hist, hist_len, st);
+    return cg_iterate<T>(c, W, g, nf, x, r, p, w, dinv, max_iter, check_every, hist, hist_len, st);
 }
 
 // Iterate the CG state held in W.scal until every field has stopped.
 template <typename T>
-sem_status cg_iterate(sem_coef c, sem_gs g, int nf, T *x, T *r, T *p, T *w, const T *dinv, int max_iter,
+sem_status cg_iterate(sem_coef c, Work &W, sem_gs g, int nf, T *x, T *r, T *p, T *w, const T *dinv, int max_iter,
                       int check_every, double *hist, int hist_len, hipStream_t st)
 {
-    Work &W = c->ws;
     const int64_t n = c->n;
     const bool f64 = sizeof(T) == 8;
     const unsigned ug = sem_update_grid(n, f64 ? 0 : 1);
@@ -109,16 +107,15 @@ sem_status cg_iterate(sem_coef c, sem_gs g, int nf, T *x, T *r, T *p, T *w, cons
 }
 
 // True FP64 residual |b - A x| / |b| per field (uses W.w and W.r as scratch).
-sem_status true_residual(sem_coef c, sem_gs g, int nf, const double *x, const double *b, double *rel,
-                         hipStream_t st)
+sem_status true_residual(sem_coef c, Work &W, const double *dinv, sem_gs g, int nf, const double *x,
+                         const double *b, double *rel, hipStream_t st)
 {
-    Work &W = c->ws;
     SEM_TRY(launch_ax<double>(c, W.w, x, nf, st));
     SEM_TRY(launch_gs<double>(W.w, nf, g, nullptr, nullptr, st));
-    HIP_TRY(sem_launch_residual(W.r, b, W.w, c->dinv, c->n, nf, st));
+    HIP_TRY(sem_launch_residual(W.r, b, W.w, dinv, c->n, nf, st));
     const double *a[2] = {W.r, b};
     double out[6];
-    SEM_TRY(dots(c, g, nf, 2, a, a, out, st));
+    SEM_TRY(dots(c, W, g, nf, 2, a, a, out, st));
     for (int f = 0; f < nf; ++f) {
         const double rr = out[0 * nf + f], bb = out[1 * nf + f];
         rel[f] = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
@@ -126,13 +123,18 @@ sem_status true_residual(sem_coef c, sem_gs g, int nf, const double *x, const do
     return SEM_OK;
 }
 
-// FP64 two-reduction Jacobi-PCG on the scratch held in c->ws (and c->dinv).
-sem_status pcg_fp64(double *x, const double *b, int nf, sem_coef c, sem_gs g, const sem_pcg_params *P,
-                           sem_pcg_info *info, hipStream_t st)
+sem_status true_residual(sem_coef c, sem_gs g, int nf, const double *x, const double *b, double *rel,
+                         hipStream_t st)
 {
-    Work &W = c->ws;
+    return true_residual(c, c->ws, c->dinv, g, nf, x, b, rel, st);
+}
+
+// FP64 two-reduction Jacobi-PCG on the scratch W and the Jacobi inverse dinv.
+sem_status pcg_fp64(double *x, const double *b, int nf, sem_coef c, sem_gs g, const sem_pcg_params *P,
+                    sem_pcg_info *info, Work &W, const double *dinv, hipStream_t st)
+{
     const double rtol[3] = {P->rtol, P->rtol, P->rtol};
-    SEM_TRY(cg_run<double>(c, g, nf, x, b, P->use_x0 != 0, W.r, W.p, W.w, c->dinv, rtol, P->max_iter,
+    SEM_TRY(cg_run<double>(c, W, g, nf, x, b, P->use_x0 != 0, W.r, W.p, W.w, dinv, rtol, P->max_iter,
                            P->check_every, nullptr, 0, st));
     // A field counts as converged only when its true residual |b - A x| / |b| meets
     // rtol.  When the recursive residual has drifted below it, the true residual
@@ -140,7 +142,7 @@ sem_status pcg_fp64(double *x, const double *b, int nf, sem_coef c, sem_gs g, co
     // its search direction.
     double tr[3];
     for (int round = 0;; ++round) {
-        SEM_TRY(true_residual(c, g, nf, x, b, tr, st));
+        SEM_TRY(true_residual(c, W, dinv, g, nf, x, b, tr, st));
         bool any = false;
         for (int f = 0; f < nf; ++f) {
             const CgScalars &s = W.h_scal[f];
@@ -150,10 +152,10 @@ sem_status pcg_fp64(double *x, const double *b, int nf, sem_coef c, sem_gs g, co
         if (!any || round >= 16) break;
         const unsigned vg = sem_vec_grid(c->n);
         HIP_TRY(hipMemcpyAsync(W.done, W.h_done, sizeof(int) * nf, hipMemcpyHostToDevice, st));
-        HIP_TRY(sem_launch_cg_replace_f64(W.r, c->dinv, g->d_owner, W.done, W.partial, c->n, nf, st));
+        HIP_TRY(sem_launch_cg_replace_f64(W.r, dinv, g->d_owner, W.done, W.partial, c->n, nf, st));
         CgFinishArgs F{W.partial, (int64_t)vg, W.scal, nullptr, 0, nf};
         HIP_TRY(sem_launch_cg_resume(&F, W.done, st));
-        SEM_TRY(cg_iterate<double>(c, g, nf, x, W.r, W.p, W.w, c->dinv, P->max_iter, P->check_every, nullptr, 0, st));
+        SEM_TRY(cg_iterate<double>(c, W, g, nf, x, W.r, W.p, W.w, dinv, P->max_iter, P->check_every, nullptr, 0, st));
     }
     CgScalars res[3];
     std::memcpy(res, W.h_scal, sizeof(CgScalars) * nf);
@@ -174,6 +176,37 @@ sem_status pcg_fp64(double *x, const double *b, int nf, sem_coef c, sem_gs g, co
             out = fail(SEM_ERR_NOT_CONVERGED, "field %d: |r|/|b| = %.3e after %d iterations", f, rel, s.iter);
     }
     return out;
+}
+
+// Arguments of sem_pcg_solve (and of its allocation-free variant).
+sem_status check_pcg_args(const double *x, const double *b, int nfields, sem_coef coef, sem_mesh msh, sem_space Xh,
+                          sem_gs gs, const sem_pcg_params *params)
+{
+    SEM_TRY(check_coef(coef, msh, Xh));
+    if (!gs || gs->msh != msh) return fail(SEM_ERR_INVALID, "gs is NULL or built for another mesh");
+    if (!params) return fail(SEM_ERR_INVALID, "params is NULL");
+    if (nfields != 1 && nfields != 3) return fail(SEM_ERR_INVALID, "nfields must be 1 or 3");
+    const sem_pcg_params &P = *params;
+    if (P.max_iter < 1) return fail(SEM_ERR_INVALID, "max_iter must be >= 1");
+    if (!std::isfinite(P.rtol)) return fail(SEM_ERR_INVALID, "rtol is not finite");
+    if (P.mixed < 0 || P.mixed > 2) return fail(SEM_ERR_INVALID, "mixed must be 0, 1 or 2");
+    if (P.mixed) {
+        if (!(coef->flags & SEM_COEF_F32)) return fail(SEM_ERR_INVALID, "mixed solve needs a coef created with SEM_COEF_F32");
+        if (P.rtol <= 0) return fail(SEM_ERR_INVALID, "mixed solve needs rtol > 0");
+    }
+    if (P.variant != 0 && P.variant != 1) return fail(SEM_ERR_INVALID, "variant must be 0 or 1");
+    if (P.variant == 1 && P.mixed != 0) return fail(SEM_ERR_INVALID, "the single-reduction form is FP64 only (mixed = 0)");
+    if (P.mixed == 1 && !(P.delta == 0.0 || (P.delta > 0.0 && P.delta < 1.0)))
+        return fail(SEM_ERR_INVALID, "delta must be 0 (default) or in (0, 1)");
+    if (P.mixed == 2) {
+        if (!(P.inner_rtol > 0.0 && P.inner_rtol < 1.0)) return fail(SEM_ERR_INVALID, "inner_rtol must be in (0, 1)");
+        if (P.inner_max_iter < 1) return fail(SEM_ERR_INVALID, "inner_max_iter must be >= 1");
+    }
+    const size_t bytes = (size_t)coef->n * nfields * 8;
+    if (bytes == 0) return SEM_OK;
+    if (!x || !b) return fail(SEM_ERR_INVALID, "x or b is NULL");
+    if (overlap(x, bytes, b, bytes)) return fail(SEM_ERR_INVALID, "x and b overlap");
+    return SEM_OK;
 }
 
 }  // namespace semi
@@ -462,7 +495,7 @@ static sem_status pcg_mixed(double *x, const double *b, int nf, sem_coef c, sem_
             const double need = (rr[f] > 0.0) ? 0.1 * P->rtol * std::sqrt(bb[f] / rr[f]) : 0.5;
             tau[f] = std::min(0.5, std::max(P->inner_rtol, need));
         }
-        SEM_TRY(cg_run<float>(c, g, nf, W.y32, W.r32, false, W.ri32, W.p32, W.w32, c->dinv32, tau,
+        SEM_TRY(cg_run<float>(c, W, g, nf, W.y32, W.r32, false, W.ri32, W.p32, W.w32, c->dinv32, tau,
                               P->inner_max_iter, std::max(1, P->check_every), nullptr, 0, st));
         for (int f = 0; f < nf; ++f) inner[f] += W.h_scal[f].iter;
         HIP_TRY(sem_launch_fcg_scale_up(W.z, W.y32, W.fcg + 2 * nf, n, nf, st));
@@ -550,30 +583,9 @@ static sem_status pcg_mixed(double *x, const double *b, int nf, sem_coef c, sem_
 sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef, sem_mesh msh, sem_space Xh,
                          sem_gs gs, const sem_pcg_params *params, sem_pcg_info *info, void *stream)
 {
-    SEM_TRY(check_coef(coef, msh, Xh));
-    if (!gs || gs->msh != msh) return fail(SEM_ERR_INVALID, "gs is NULL or built for another mesh");
-    if (!params) return fail(SEM_ERR_INVALID, "params is NULL");
-    if (nfields != 1 && nfields != 3) return fail(SEM_ERR_INVALID, "nfields must be 1 or 3");
+    SEM_TRY(check_pcg_args(x, b, nfields, coef, msh, Xh, gs, params));
     const sem_pcg_params &P = *params;
-    if (P.max_iter < 1) return fail(SEM_ERR_INVALID, "max_iter must be >= 1");
-    if (!std::isfinite(P.rtol)) return fail(SEM_ERR_INVALID, "rtol is not finite");
-    if (P.mixed < 0 || P.mixed > 2) return fail(SEM_ERR_INVALID, "mixed must be 0, 1 or 2");
-    if (P.mixed) {
-        if (!(coef->flags & SEM_COEF_F32)) return fail(SEM_ERR_INVALID, "mixed solve needs a coef created with SEM_COEF_F32");
-        if (P.rtol <= 0) return fail(SEM_ERR_INVALID, "mixed solve needs rtol > 0");
-    }
-    if (P.variant != 0 && P.variant != 1) return fail(SEM_ERR_INVALID, "variant must be 0 or 1");
-    if (P.variant == 1 && P.mixed != 0) return fail(SEM_ERR_INVALID, "the single-reduction form is FP64 only (mixed = 0)");
-    if (P.mixed == 1 && !(P.delta == 0.0 || (P.delta > 0.0 && P.delta < 1.0)))
-        return fail(SEM_ERR_INVALID, "delta must be 0 (default) or in (0, 1)");
-    if (P.mixed == 2) {
-        if (!(P.inner_rtol > 0.0 && P.inner_rtol < 1.0)) return fail(SEM_ERR_INVALID, "inner_rtol must be in (0, 1)");
-        if (P.inner_max_iter < 1) return fail(SEM_ERR_INVALID, "inner_max_iter must be >= 1");
-    }
-    const size_t bytes = (size_t)coef->n * nfields * 8;
-    if (bytes == 0) return SEM_OK;
-    if (!x || !b) return fail(SEM_ERR_INVALID, "x or b is NULL");
-    if (overlap(x, bytes, b, bytes)) return fail(SEM_ERR_INVALID, "x and b overlap");
+    if ((size_t)coef->n * nfields == 0) return SEM_OK;
     hipStream_t st = S(stream);
     SEM_TRY(gs_upload(gs));
     SEM_TRY(ensure_dinv(coef, gs, st));
@@ -584,7 +596,7 @@ sem_status sem_pcg_solve(double *x, const double *b, int nfields, sem_coef coef,
     if (Q.mixed == 1) return pcg_mixed_reliable(x, b, nfields, coef, gs, &Q, info, st);
     if (Q.mixed == 2) return pcg_mixed(x, b, nfields, coef, gs, &Q, info, st);
     if (Q.variant == 1) return pcg_cg1(x, b, nfields, coef, gs, &Q, info, st);
-    return pcg_fp64(x, b, nfields, coef, gs, &Q, info, st);
+    return pcg_fp64(x, b, nfields, coef, gs, &Q, info, coef->ws, coef->dinv, st);
 }
 
 }  // extern "C"

@@ -368,19 +368,31 @@ sem_status launch_ax(sem_coef c, T *w, const T *u, int nf, hipStream_t st)
 
 // Jacobi inverse (point Jacobi: exact assembled diagonal), cached per (coef, gs).
 sem_status ensure_dinv(sem_coef c, sem_gs g, hipStream_t st);
+// The same inverse written to dinv (n_p values), no caching and no allocation.
+sem_status compute_dinv(sem_coef c, sem_gs g, double *dinv, hipStream_t st);
 // CG scratch of a coef handle for nf fields (and the FP32 vectors when mixed).
 sem_status ensure_work(sem_coef c, int nf, bool mixed);
 // Row stride of the CG reduction partials (the widest grid of the CG kernels); the
 // partial buffer holds (4 nf + 3) rows.
 int64_t cg_partial_stride(sem_coef c);
 // FP64 two-reduction Jacobi-PCG (sem_pcg_solve with mixed = 0, variant = 0) on the
-// scratch of c->ws and the Jacobi inverse c->dinv; P->rtol is the final target.
+// scratch W (r, p, w, partial, scal, job64, dots, done and their host mirrors) and the
+// Jacobi inverse dinv; P->rtol is the final target.
 sem_status pcg_fp64(double *x, const double *b, int nf, sem_coef c, sem_gs g, const sem_pcg_params *P,
-                    sem_pcg_info *info, hipStream_t st);
-// Owner-weighted dots on the device: out[q*nf + f] = sum_owned a_q b_q (field f).
+                    sem_pcg_info *info, Work &W, const double *dinv, hipStream_t st);
+// Argument checks of sem_pcg_solve (SEM_OK for a valid call, including n_p = 0).
+sem_status check_pcg_args(const double *x, const double *b, int nfields, sem_coef coef, sem_mesh msh, sem_space Xh,
+                          sem_gs gs, const sem_pcg_params *params);
+// Owner-weighted dots on the device: out[q*nf + f] = sum_owned a_q b_q (field f), on
+// the partial rows and result slots of W (c->ws in the second form).
+sem_status dots(sem_coef c, Work &W, sem_gs g, int nf, int nd, const double *const *a, const double *const *b,
+                double *host_out, hipStream_t st);
 sem_status dots(sem_coef c, sem_gs g, int nf, int nd, const double *const *a, const double *const *b,
                 double *host_out, hipStream_t st);
-// True FP64 residual |b - A x| / |b| per field (uses W.w and W.r as scratch).
+// True FP64 residual |b - A x| / |b| per field (uses W.w and W.r as scratch; c->ws and
+// c->dinv in the second form).
+sem_status true_residual(sem_coef c, Work &W, const double *dinv, sem_gs g, int nf, const double *x,
+                         const double *b, double *rel, hipStream_t st);
 sem_status true_residual(sem_coef c, sem_gs g, int nf, const double *x, const double *b, double *rel,
                          hipStream_t st);
 

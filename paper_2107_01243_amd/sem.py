@@ -74,6 +74,8 @@ _SIGS = {
     "sem_jacobi_inverse": ([_vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "sem_pcg_solve": ([_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.POINTER(PcgParams),
                        C.POINTER(PcgInfo), _vp], C.c_int),
+    "sem_pcg_solve_noalloc": ([_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.POINTER(PcgParams),
+                               C.POINTER(PcgInfo), _vp], C.c_int),
     "sem_stream_triad": ([_vp, _vp, _vp, C.c_double, C.c_int64, _vp], C.c_int),
     "sem_gmres_solve": ([_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(GmresParams), C.POINTER(PcgInfo), _vp],
                         C.c_int),
@@ -357,6 +359,31 @@ def pcg_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, nfields: int = 1, 
         raise SemError(st, _L.sem_last_error().decode(errors="replace"))
     return out
 
+
+def pcg_solve_noalloc(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, nfields: int = 1, rtol: float = 1e-10,
+                      max_iter: int = 100000, check_every: int = 25, use_x0: bool = False, stream=None,
+                      raise_on_fail: bool = True):
+    """The FP64 Jacobi-PCG solve of pcg_solve on the library's fixed device workspace
+    (no device allocation; n_p * nfields <= NOALLOC_MAX_POINTS; the gs handle must
+    already be resident, e.g. after one gs_op).  Returns one info dict per field."""
+    _dev(x, nfields * msh.n, "x")
+    _dev(b, nfields * msh.n, "b")
+    if x.dtype != torch.float64 or b.dtype != torch.float64:
+        raise TypeError("x and b must be float64")
+    P = PcgParams(float(rtol), int(max_iter), int(check_every), 0, 1e-4, 1, int(bool(use_x0)), 0.0, 0)
+    info = (PcgInfo * nfields)()
+    st = _L.sem_pcg_solve_noalloc(_ptr(x), _ptr(b), nfields, coef._h, msh._h, Xh._h, gs._h, C.byref(P), info,
+                                  _stream(stream))
+    out = [info[f].as_dict() for f in range(nfields)]
+    for d in out:
+        d["status"] = st
+    if st != SEM_OK and raise_on_fail:
+        raise SemError(st, _L.sem_last_error().decode(errors="replace"))
+    return out
+
+
+# SEM_NOALLOC_MAX_POINTS of sem.h
+NOALLOC_MAX_POINTS = 1 << 21
 
 GMRES_PRECOND = {"jacobi": 0, "schwarz": 1}
 
