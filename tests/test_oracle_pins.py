@@ -558,6 +558,56 @@ def test_schwarz_local_operator_on_affine_elements():
         assert np.abs(ext[np.ix_(inner, inner)]).max() == 0.0
 
 
+def _extended_1d(lx, L):
+    """Stiffness and (lumped) mass of a 1-D chain, assembled from element matrices and
+    then restricted to the middle element's nodes: a linear element of the middle
+    element's first GLL spacing at each end (outer node Dirichlet), and the middle
+    element, a degree lx-1 Lagrange element on the GLL points of [0, L] whose stiffness
+    is integrated exactly by Gauss-Legendre quadrature of the basis derivatives and whose
+    mass is the GLL-quadrature (diagonal) mass."""
+    N = lx - 1
+    xi = np.sort(np.concatenate(([-1.0, 1.0], np.polynomial.legendre.Legendre.basis(N).deriv().roots())))
+    x = (xi + 1.0) * L / 2.0
+    V = np.vander(x, lx, increasing=True)
+    C = np.linalg.inv(V)                           # column j: monomial coefficients of l_j
+    q, wq = np.polynomial.legendre.leggauss(lx + 2)
+    xq = (q + 1.0) * L / 2.0
+    dphi = np.array([np.polynomial.polynomial.polyval(xq, np.polynomial.polynomial.polyder(C[:, j]))
+                     for j in range(lx)])         # [basis, quadrature point]
+    Km = (dphi * (wq * L / 2.0)) @ dphi.T
+    wg = np.array([np.polynomial.polynomial.polyval(x, C[:, j]) for j in range(lx)])  # identity at nodes
+    # GLL weights: exact integrals of the Lagrange basis (degree N <= 2N - 1 exactness)
+    wgl = np.array([np.polynomial.polynomial.polyval(xq, C[:, j]) @ (wq * L / 2.0) for j in range(lx)])
+    Mm = np.diag(wgl)
+    h = x[1] - x[0]
+    Klin = np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
+    Mlin = np.eye(2) * h / 2.0                     # lumped linear mass
+    n = lx + 2                                     # outer node, the element's nodes, outer node
+    K = np.zeros((n, n))
+    M = np.zeros((n, n))
+    K[1:lx + 1, 1:lx + 1] += Km
+    M[1:lx + 1, 1:lx + 1] += Mm
+    for a, b in ((0, 1), (lx, lx + 1)):
+        K[np.ix_([a, b], [a, b])] += Klin
+        M[np.ix_([a, b], [a, b])] += Mlin
+    assert np.allclose(wg, np.eye(lx))
+    return K[1:lx + 1, 1:lx + 1], M[1:lx + 1, 1:lx + 1]
+
+
+def test_schwarz_extension_matches_assembled_linear_segments():
+    """The extension of the local Schwarz operator has the magnitude its reading states:
+    on an undeformed box, the oracle's separable local operator equals the Kronecker
+    form built from an independent 1-D assembly of the element plus one linear segment
+    of the first GLL spacing at each end (Dirichlet beyond), with h1 and h2 both on."""
+    for nx, lx in ((2, 4), (1, 6), (3, 8)):
+        P = oracle.Problem(nx, lx, 0.0, h1=0.7, h2=3.0).schwarz_setup()
+        K, M = _extended_1d(lx, 1.0 / nx)
+        ref = 0.7 * (np.kron(M, np.kron(M, K)) + np.kron(M, np.kron(K, M)) + np.kron(K, np.kron(M, M))) \
+            + 3.0 * np.kron(M, np.kron(M, M))
+        for e in (0, nx ** 3 - 1):
+            np.testing.assert_allclose(P._loc[e], ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
 def test_schwarz_coarse_correction_recovers_coarse_errors():
     """For r = A P u0 (u0 on the free vertices) an exact coarse solve gives back P u0."""
     P = oracle.Problem(3, 5, 0.05).schwarz_setup()
