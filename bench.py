@@ -54,15 +54,19 @@ def log(msg):
 
 
 PROFILE_MD = os.path.join(ROOT, "profiles", "pcg_32x32x32_lx8_kernels.md")
+PROFILE_LX12_MD = os.path.join(ROOT, "profiles", "velocity3_48x48x48_lx12_kernels.md")
+# the kernel sources a profile summary's counters describe (hashed into the summary)
+PROFILE_SOURCES = ["paper_2107_01243_amd/csrc/ax_kernels.hip", "paper_2107_01243_amd/csrc/vec_kernels.hip",
+                   "paper_2107_01243_amd/csrc/sem_kernels.h", "paper_2107_01243_amd/csrc/vec_kernels.h"]
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the summary is
-    missing or the kernel sources changed since it was taken."""
+def profiled_traffic(kernel, md=None):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy; PROFILE_MD unless md is given), or
+    None when the summary is missing or the kernel sources changed since it was taken."""
     import hashlib
     try:
-        text = open(PROFILE_MD).read()
+        text = open(md or PROFILE_MD).read()
         blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
         h = hashlib.sha256()
         for f in blob["sources"]:
@@ -73,6 +77,102 @@ def profiled_traffic(kernel):
         return k["fetch_bytes"] + k["write_bytes"]
     except (OSError, KeyError, IndexError, ValueError):
         return None
+
+
+def _short_name(name):
+    """Kernel name without 'void ' and without its argument list."""
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0 and i > 0:
+            return name[:i]
+    return name
+
+
+def _csv_rows(folder, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(folder, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {folder}")
+    with open(files[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, title, workload, commands, sources, window=None):
+    """Write a rocprofv3 summary (markdown table plus the machine-readable block that
+    profiled_traffic reads) from a --kernel-trace --stats run and two --pmc runs
+    (FETCH_SIZE, WRITE_SIZE).  Counter readings are scaled by what the same counter
+    reads for the largest plain device copy in the run (1 GiB moved each way)."""
+    import hashlib
+    from collections import defaultdict
+    stats = _csv_rows(trace_dir, "kernel_stats.csv")
+    per = {}
+    for r in stats:
+        per[_short_name(r["Name"])] = {"calls": int(r["Calls"]), "avg_us": float(r["AverageNs"]) / 1e3,
+                                       "total_ms": float(r["TotalDurationNs"]) / 1e6,
+                                       "pct": float(r["Percentage"])}
+
+    def counter(folder, cname):
+        rows = [r for r in _csv_rows(folder, "counter_collection.csv") if r["Counter_Name"] == cname]
+        acc = defaultdict(list)
+        copy = []
+        for r in rows:
+            k = _short_name(r["Kernel_Name"])
+            acc[k].append(float(r["Counter_Value"]))
+            if k == "__amd_rocclr_copyBuffer":
+                copy.append((int(r["Dispatch_Id"]), int(r["Grid_Size"]), float(r["Counter_Value"])))
+        # the reference copy is the profile run's first large copy (the profile modes of
+        # this script issue it before anything else)
+        gmax = max(c[1] for c in copy)
+        _, grid, kib = min(c for c in copy if c[1] == gmax)
+        return {k: sum(v) / len(v) for k, v in acc.items()}, grid, kib
+
+    fetch, fgrid, fkib = counter(fetch_dir, "FETCH_SIZE")
+    write, wgrid, wkib = counter(write_dir, "WRITE_SIZE")
+    moved_kib = 1 << 20
+    fscale, wscale = moved_kib / fkib, moved_kib / wkib
+    h = hashlib.sha256()
+    for f in sources:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    lines = [f"# rocprofv3: {title}", "", workload, "",
+             "Commands (on the GPU host; /root/repo is the repository root):", ""]
+    lines += ["    " + c for c in commands]
+    if window:
+        # average duration of a run of consecutive launches of one kernel (the launches a
+        # benchmark times), from the kernel trace
+        wname, first, count = window[0], int(window[1]), int(window[2])
+        trace = sorted(_csv_rows(trace_dir, "kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
+        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace
+                if _short_name(r["Kernel_Name"]) == wname][first:first + count]
+        lines += ["", f"Launches {first + 1}-{first + len(durs)} of `{wname}` (the ones the benchmark times): "
+                  f"average {sum(durs) / max(1, len(durs)):.2f} us over {len(durs)} launches."]
+    lines += ["", f"Counter scaling from the plain 1 GiB device copy (`__amd_rocclr_copyBuffer`, grid {fgrid}) in "
+              f"the same run: FETCH_SIZE reads {fkib:.1f} KiB for {moved_kib} KiB moved -> x{fscale:.4f}; "
+              f"WRITE_SIZE reads {wkib:.1f} KiB -> x{wscale:.4f}. Columns below are per launch, scaled.", "",
+              "| kernel | calls | avg us | total ms | % | fetch MB | write MB | eff. GB/s |",
+              "|---|---|---|---|---|---|---|---|"]
+    blob = {"source_sha256": h.hexdigest(), "sources": list(sources), "fetch_scale": fscale,
+            "write_scale": wscale, "kernels": {}}
+    for k, v in sorted(per.items(), key=lambda kv: -kv[1]["total_ms"]):
+        fb = fetch.get(k, 0.0) * 1024 * fscale
+        wb = write.get(k, 0.0) * 1024 * wscale
+        eff = (fb + wb) / (v["avg_us"] * 1e-6) / 1e9 if v["avg_us"] > 0 else 0.0
+        lines.append(f"| `{k}` | {v['calls']} | {v['avg_us']:.2f} | {v['total_ms']:.3f} | {v['pct']:.2f} | "
+                     f"{fb / 1e6:.1f} | {wb / 1e6:.1f} | {eff:.0f} |")
+        blob["kernels"][k] = {"avg_us": round(v["avg_us"], 3), "calls": v["calls"],
+                              "fetch_bytes": int(round(fb)), "write_bytes": int(round(wb))}
+    lines += ["", "Machine-readable (read by bench.py; `source_sha256` covers the listed kernel sources):", "",
+              "```json", json.dumps(blob, indent=1), "```", ""]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines))
+    return out_md
 
 
 def _cpu_model():
@@ -158,6 +258,149 @@ def cpu_baseline(wl, gpu_iters, full_solve=False, mixed=None):
     return out
 
 
+LX12_KERNELS = {"ax_f64_poisson_1field": "sem::k_ax_helm_lean<12, double, 1, 0>",
+                "ax_f64_helmholtz_1field": "sem::k_ax_helm_lean<12, double, 1, 1>",
+                "ax_f64_helmholtz_3field": "sem::k_ax_helm_lean<12, double, 3, 1>",
+                "ax_f32_helmholtz_3field": "sem::k_ax_helm_lean<12, float, 3, 1>",
+                "adjoint_f64": "sem::k_ax_adjoint_lean<12, double>"}
+LX12_WORDS = {"ax_f64_poisson_1field": (8, 8), "ax_f64_helmholtz_1field": (9, 8),
+              "ax_f64_helmholtz_3field": (13, 8), "ax_f32_helmholtz_3field": (13, 4),
+              "adjoint_f64": (9, 8)}
+
+
+def lx12_section(stream):
+    """The high-order velocity workload after the timed steps: 48^3 curved elements,
+    lx = 12 (191M local points per field), h1 = 1/5000, h2 = 1/5e-4.  The lx = 12
+    operators (one and three fields, FP64 and FP32, and the h1-adjoint), each as the
+    average of five back-to-back launches from HIP events on the launch stream against
+    its algorithmic bytes per point, and the batched three-field mixed solve to 1e-10
+    (reliable updates; median of two after one untimed solve)."""
+    import torch
+
+    import workloads
+    from paper_2107_01243_amd import sem
+
+    wl = workloads.WORKLOADS["velocity3_48x48x48_lx12"]
+    t0 = time.time()
+    P = sem.BoxProblem.build(wl.nx, wl.lx, wl.eps, fp32=True)
+    P.xyz = None
+    n = P.n
+    log(f"lx=12 setup {time.time() - t0:.1f}s, n_local={n}")
+
+    def t_ms(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    u3 = torch.from_numpy(np.concatenate([workloads.uniform(n, sd) for sd in (0, 5, 6)])).cuda()
+    w3 = torch.empty_like(u3)
+    u, w = u3[:n], w3[:n]
+    ms = {}
+    P.coef.set_helmholtz(1.0, 0.0)
+    ms["ax_f64_poisson_1field"] = t_ms(lambda: sem.ax_helm(w, u, P.coef, P.msh, P.Xh))
+    P.coef.set_helmholtz(wl.h1, wl.h2)
+    ms["ax_f64_helmholtz_1field"] = t_ms(lambda: sem.ax_helm(w, u, P.coef, P.msh, P.Xh))
+    ms["ax_f64_helmholtz_3field"] = t_ms(lambda: sem.ax_helm(w3, u3, P.coef, P.msh, P.Xh, 3))
+    g = torch.empty_like(u)
+    ms["adjoint_f64"] = t_ms(lambda: sem.ax_helm_adjoint(g, u, w, P.coef, P.msh, P.Xh))
+    del g
+    f3, v3 = u3.float(), w3.float()
+    ms["ax_f32_helmholtz_3field"] = t_ms(lambda: sem.ax_helm(v3, f3, P.coef, P.msh, P.Xh, 3))
+    del f3, v3, u3, w3, u, w
+    torch.cuda.empty_cache()
+    res = {"elements": wl.nelv, "lx": wl.lx, "n_local_per_field": n, "h1": wl.h1, "h2": wl.h2}
+    for k, t in ms.items():
+        words, prec = LX12_WORDS[k]
+        gbs = words * prec * n / (t / 1e3) / 1e9
+        res[k] = {"ms": round(t, 3), "bytes_per_point": words * prec, "GBs": round(gbs, 1),
+                  "frac": round(gbs / HBM_PEAK_GBS, 4),
+                  "traffic": profiled_traffic(LX12_KERNELS[k], PROFILE_LX12_MD)}
+        log(f"lx=12 {k}: {t:.3f} ms, {gbs:.0f} GB/s")
+    bl = np.concatenate([workloads.uniform(n, sd) for sd in workloads.SEED_RHS_FIELDS])
+    b = P.assemble(torch.from_numpy(bl).cuda(), nfields=3)
+    del bl
+    x = torch.zeros_like(b)
+    ts, info = [], None
+    for k in range(3):
+        x.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        info = sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, nfields=3, rtol=wl.rtol, mixed="reliable",
+                             check_every=10)
+        torch.cuda.synchronize()
+        if k > 0:
+            ts.append(time.perf_counter() - t1)
+    res["batched_mixed_solve_s"] = round(float(np.median(ts)), 4)
+    res["batched_mixed_replacements"] = [d["iters"] for d in info]
+    res["batched_mixed_fp32_iters"] = [d["inner_iters"] for d in info]
+    res["batched_mixed_true_rel_res"] = [d["true_rel_res"] for d in info]
+    log(f"lx=12 batched mixed solve {res['batched_mixed_solve_s']:.3f} s")
+    del P, b, x
+    torch.cuda.empty_cache()
+    return res
+
+
+def profile_lx12(stream):
+    """The kernels of the high-order velocity workload for a profiler run (see
+    --profile-lx12); a plain device copy of 2^27 doubles first, the reference for
+    scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    import workloads
+    from paper_2107_01243_amd import sem
+
+    torch.cuda.set_device(0)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    del src, dst
+    wl = workloads.WORKLOADS["velocity3_48x48x48_lx12"]
+    P = sem.BoxProblem.build(wl.nx, wl.lx, wl.eps, fp32=True)
+    P.xyz = None
+    n = P.n
+    u3 = torch.from_numpy(np.concatenate([workloads.uniform(n, sd) for sd in (0, 5, 6)])).cuda()
+    w3 = torch.empty_like(u3)
+    u, w = u3[:n], w3[:n]
+    P.coef.set_helmholtz(1.0, 0.0)
+    for _ in range(5):
+        sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
+    P.coef.set_helmholtz(wl.h1, wl.h2)
+    for _ in range(5):
+        sem.ax_helm(w, u, P.coef, P.msh, P.Xh)
+    for _ in range(5):
+        sem.ax_helm(w3, u3, P.coef, P.msh, P.Xh, 3)
+    g = torch.empty_like(u)
+    for _ in range(5):
+        sem.ax_helm_adjoint(g, u, w, P.coef, P.msh, P.Xh)
+    del g
+    f3, v3 = u3.float(), w3.float()
+    for _ in range(5):
+        sem.ax_helm(v3, f3, P.coef, P.msh, P.Xh, 3)
+    del f3, v3, w3
+    torch.cuda.empty_cache()
+    bl = np.concatenate([workloads.uniform(n, sd) for sd in workloads.SEED_RHS_FIELDS])
+    b = P.assemble(torch.from_numpy(bl).cuda(), nfields=3)
+    del bl
+    x = torch.zeros_like(b)
+    sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, nfields=3, rtol=0.0, max_iter=10, check_every=10,
+                  raise_on_fail=False)
+    x.zero_()
+    sem.pcg_solve(x, b, P.coef, P.msh, P.Xh, P.gs, nfields=3, rtol=wl.rtol, mixed="reliable", check_every=10)
+    hf = torch.full((n,), wl.h1, dtype=torch.float64, device="cuda")
+    P.coef.set_helmholtz(hf, wl.h2)
+    x1 = torch.zeros_like(u)
+    sem.pcg_solve(x1, b[:n].contiguous(), P.coef, P.msh, P.Xh, P.gs, rtol=0.0, max_iter=10, check_every=10,
+                  raise_on_fail=False)
+    torch.cuda.synchronize()
+    log("lx=12 profile pass done")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,18 +411,35 @@ def main():
     ap.add_argument("--no-oracle-solve", action="store_true",
                     help="CPU baseline without the oracle's full PCG solve (and the solution errors)")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-lx12", action="store_true",
+                    help="skip the high-order velocity workload (48^3 elements, lx = 12, three fields)")
     ap.add_argument("--no-pressure", action="store_true", help="skip the GMRES + Schwarz solve")
     ap.add_argument("--proj-steps", type=int, default=8,
                     help="solves of the slowly varying load sequence with a 20-vector projection space "
                          "(0: skip)")
     ap.add_argument("--inner-rtol", type=float, default=1e-4, dest="inner_rtol",
                     help="nominal inner tolerance of the mixed solve")
+    ap.add_argument("--profile-lx12", action="store_true", dest="profile_lx12",
+                    help="short run for rocprofv3 on the high-order velocity workload (48^3 elements, lx = 12): "
+                         "a 1 GiB device copy, five launches each of the lx = 12 operators (FP64 one and three "
+                         "fields, FP32 three fields, the h1-adjoint), ten FP64 three-field CG iterations, "
+                         "the batched mixed solve and ten FP64 CG iterations with an h1 field")
     ap.add_argument("--profile", action="store_true",
-                    help="short run for rocprofv3: one plain device copy of 2^27 doubles (reference "
+                    help="short run for rocprofv3: one plain device copy of 2^27 doubles first (reference "
                          "for counter scaling), --reps ax_helm launches, one gs_op, 20 PCG iterations "
                          "in each form, five h1-adjoint and five batched three-field operator launches "
                          "per precision, and nine projection-space updates")
+    ap.add_argument("--summarize", nargs=4, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "OUT_MD"),
+                    help="write a profile summary from rocprofv3 CSV output (no GPU); with --title, "
+                         "--workload-text, --command (repeatable)")
+    ap.add_argument("--title", default="")
+    ap.add_argument("--workload-text", default="", dest="workload_text")
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--window", nargs=3, metavar=("KERNEL", "FIRST", "COUNT"), default=None)
     a = ap.parse_args()
+    if a.summarize:
+        summarize_profile(*a.summarize, a.title, a.workload_text, a.command, PROFILE_SOURCES, a.window)
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the multi-GPU path "
               "is designed but not implemented.", file=sys.stderr)
@@ -190,8 +450,17 @@ def main():
     import workloads
     from paper_2107_01243_amd import sem
 
+    if a.profile_lx12:
+        profile_lx12(torch.cuda.current_stream())
+        return
     wl = workloads.WORKLOADS["poisson_32x32x32_lx8"]
     torch.cuda.set_device(0)
+    if a.profile:
+        # the counter reference first: a plain device copy of 2^27 doubles (1 GiB)
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        del src, dst
     t0 = time.time()
     P = sem.BoxProblem.build(wl.nx, wl.lx, wl.eps, fp32=True)
     u = torch.from_numpy(workloads.uniform(P.n, workloads.SEED_U)).cuda()
@@ -512,6 +781,14 @@ def main():
         out.update({
             "pcg_mixed_solve_s": round(float(np.median(rec["mixed_s"])), 4),
             "pcg_mixed_method": "FP32 Jacobi-PCG with FP64 reliable updates (residual replacement)",
+            "pcg_mixed_precision_roles": ("reliable updates: FP32 operator, gather-scatter, preconditioner and "
+                                          "Krylov vectors; FP64 solution update (x += y at each replacement), "
+                                          "FP64 true residual b - A x (which replaces the FP32 one and decides "
+                                          "convergence), FP64 accumulation of every dot product -- an FP64 "
+                                          "iterative refinement whose inner FP32 CG keeps its search direction. "
+                                          "Flexible CG (pcg_fcg_*): FP64 outer residual, dots, direction and "
+                                          "solution update around FP32 inner solves that restart their Krylov "
+                                          "space."),
             "pcg_mixed_replacements": int(np.median(rec["outer"])),
             "pcg_mixed_fp32_iters": int(np.median(rec["inner"])),
             "pcg_mixed_true_rel_res": float(np.max(rec["trm"])),
@@ -565,9 +842,11 @@ def main():
             "proj_true_rel_res_max": float(max(r[2] for r in proj_rec)),
             "proj_speedup_after_4": round(proj_rec[0][0] / float(np.mean([r[0] for r in warm])), 3),
         })
+    del P, u, w, x, b, us, ws
+    torch.cuda.empty_cache()
+    if not a.no_lx12:
+        out["velocity3_48x48x48_lx12"] = lx12_section(stream)
     if not a.no_cpu_baseline:
-        del P, u, w, x, b, us, ws
-        torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(wl, out["pcg_fp64_iters"], full_solve=bool(sols), mixed=sols)
         if sols:
             out["solution_err_vs_oracle"] = out["cpu_baseline"].pop("solution_err_vs_oracle")

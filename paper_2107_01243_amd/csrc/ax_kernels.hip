@@ -23,6 +23,7 @@
 // instantiations build in parallel; it exports plain host launchers.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "sem_kernels.h"
 
@@ -30,6 +31,7 @@
 #error "compile with -DSEM_LX=<lx>"
 #endif
 #define SEM_BOUNDS(NT) __launch_bounds__((NT))
+#define SEM_BOUNDS2(NT, W) __launch_bounds__((NT)) __attribute__((amdgpu_waves_per_eu((W))))
 
 namespace sem {
 
@@ -66,8 +68,16 @@ struct Shape {
         }
         return best;
     }
-    static constexpr int EPB = pick();
+#ifndef SEM_LEAN_LX
+#define SEM_LEAN_LX 10
+#endif
+    // lx >= SEM_LEAN_LX: the register-lean kernels, one element per workgroup, with a
+    // floor on the waves per SIMD the register allocation must leave room for (two
+    // FP64 / four FP32 up to lx = 12, half that above)
+    static constexpr bool LEAN = LX >= SEM_LEAN_LX;
+    static constexpr int EPB = LEAN ? 1 : pick();
     static constexpr int NT = EPB * NP;
+    static constexpr int MINW = !LEAN ? 1 : (sizeof(T) == 8 ? (LX <= 12 ? 2 : 1) : (LX <= 12 ? 4 : 2));
 };
 
 template <int LX, typename T>
@@ -158,6 +168,97 @@ __device__ __forceinline__ void dtmul(const DEo<LX, T> &D, const T (&in)[LX], T 
         out[H] = c;
     }
 }
+
+// Where a kernel reads D from.  DArg: the kernel-argument copy (wave-uniform values
+// the compiler keeps in scalar registers; right when they fit, as in FP32 and up to
+// lx = 8 in FP64).  DMem: a copy in device memory read with scalar loads one row at a
+// time where it is used; at lx = 12 in FP64 the 72 doubles of the even-odd D exceed the
+// scalar register file, and holding them costs a spill to vector-register lanes plus
+// two v_readlane per use (more VALU instructions than the FMAs themselves).
+template <int LX, typename T>
+struct DArg {
+    const DEo<LX, T> &D;
+    __device__ void mul(const T (&in)[LX], T (&out)[LX]) const { dmul<LX, T>(D, in, out); }
+    __device__ void tmul(const T (&in)[LX], T (&out)[LX]) const { dtmul<LX, T>(D, in, out); }
+};
+
+// p + 0 with the 0 opaque to the optimiser: loads through the result are not merged
+// with, or moved ahead of, loads through another such pointer; the address space of
+// p is kept (an opaque pointer would turn global loads into flat ones).
+template <typename T>
+__device__ __forceinline__ const T *fresh(const T *p)
+{
+    int64_t z = 0;
+    asm volatile("" : "+s"(z));
+    return p + z;
+}
+
+template <int LX, typename T>
+struct DMem {
+    const DEo<LX, T> *Dg;
+    __device__ void mul(const T (&in)[LX], T (&out)[LX]) const
+    {
+        constexpr int H = LX / 2, N = LX - 1;
+        T e[H > 0 ? H : 1], o[H > 0 ? H : 1];
+#pragma unroll
+        for (int l = 0; l < H; ++l) {
+            e[l] = in[l] + in[N - l];
+            o[l] = in[l] - in[N - l];
+        }
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const DEo<LX, T> *R = fresh(Dg);  // this row's constants loaded here
+            T se = R->S[m * H] * e[0];
+            T ao = R->A[m * H] * o[0];
+#pragma unroll
+            for (int l = 1; l < H; ++l) {
+                se = fma(R->S[m * H + l], e[l], se);
+                ao = fma(R->A[m * H + l], o[l], ao);
+            }
+            if constexpr (LX % 2 == 1) se = fma(R->cm[m], in[H], se);
+            out[m] = ao + se;
+            out[N - m] = ao - se;
+        }
+        if constexpr (LX % 2 == 1) {
+            const DEo<LX, T> *R = fresh(Dg);
+            T c = T(0);
+#pragma unroll
+            for (int l = 0; l < H; ++l) c = fma(R->rm[l], o[l], c);
+            out[H] = c;
+        }
+    }
+    __device__ void tmul(const T (&in)[LX], T (&out)[LX]) const
+    {
+        constexpr int H = LX / 2, N = LX - 1;
+        T e[H > 0 ? H : 1], o[H > 0 ? H : 1];
+#pragma unroll
+        for (int l = 0; l < H; ++l) {
+            e[l] = in[l] + in[N - l];
+            o[l] = in[l] - in[N - l];
+        }
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const DEo<LX, T> *R = fresh(Dg);
+            T se = R->A[m] * e[0];
+            T ao = R->S[m] * o[0];
+#pragma unroll
+            for (int l = 1; l < H; ++l) {
+                se = fma(R->A[l * H + m], e[l], se);
+                ao = fma(R->S[l * H + m], o[l], ao);
+            }
+            if constexpr (LX % 2 == 1) se = fma(R->rm[m], in[H], se);
+            out[m] = ao + se;
+            out[N - m] = ao - se;
+        }
+        if constexpr (LX % 2 == 1) {
+            const DEo<LX, T> *R = fresh(Dg);
+            T c = T(0);
+#pragma unroll
+            for (int l = 0; l < H; ++l) c = fma(R->cm[l], o[l], c);
+            out[H] = c;
+        }
+    }
+};
 
 // Reference-space gradient of one field held as the lane's t-pencil `u`.
 // Returns ur, us, ut as t-pencils.  Uses both LDS buffers; ends synchronised.
@@ -325,7 +426,7 @@ __device__ __forceinline__ void add_mass(const RowCoef<LX, T, GEN> &c, const T (
 // ------------------------------------------------------------------ w = A_L u
 // NF fields share one read of G (and B, h1, h2).
 template <int LX, typename T, int NF, bool GEN>
-__global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo<LX, T> D)
+__global__ SEM_BOUNDS2((Shape<LX, T>::NT), (Shape<LX, T>::MINW)) void k_ax_helm(AxArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
     __shared__ Lds<LX, T> lds;
@@ -368,7 +469,7 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_helm(AxArgs<T> A, DEo<LX, T>
 // w = A_L u.  Either way the workgroup's partial sum of v . w (v = p or u) is written:
 // v^T A v by the unassembled identity of Eq. 10.
 template <int LX, typename T, int NF, bool GEN, bool CG1>
-__global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DEo<LX, T> D)
+__global__ SEM_BOUNDS2((Shape<LX, T>::NT), (Shape<LX, T>::MINW)) void k_cg_matvec(CgMatvecArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
     static_assert(S::NT >= 64, "the partial-sum reduction needs a full first wave");
@@ -449,6 +550,530 @@ __global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_cg_matvec(CgMatvecArgs<T> A, DE
             if (tid == 0) A.partial[(int64_t)q * gridDim.x + blockIdx.x] = v;
         }
     }
+}
+
+// ------------------------------------------------------------------ register-lean variants
+// At large lx a lane's six G pencils (6 lx words) held next to a field's pencils
+// exhaust the register file (one wave per SIMD at lx = 12 in FP64), which leaves a
+// compute unit one workgroup that alternates between loading and computing.  The
+// lean kernels (lx >= SEM_LEAN_LX) hold nothing across the phases of a field: G,
+// h1, B and dinv are read in chunks of ceil(lx/2) points where they are used, the r
+// and s derivatives run one after the other, and one element is one workgroup.  The
+// registers saved let two (FP64) or four (FP32) waves share a SIMD, so the loads of
+// one workgroup overlap the arithmetic of others.  With three fields the chunks are
+// read again for every field with ordinary (cached) loads: the first field brings
+// them from HBM, the other two find them in the cache.
+
+template <bool NTL, typename T>
+__device__ __forceinline__ T ldx(const T *p)
+{
+    if constexpr (NTL) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+// Reference-space gradient, the r and s derivatives sequenced to keep one pencil pair
+// live at a time.  Same LDS protocol as grad (both buffers, ends synchronised).
+template <int LX, typename T, typename DS>
+__device__ __forceinline__ void grad_lean(const DS &D, const T (&u)[LX], T *s0, T *s1, int a, int b,
+                                          T (&ur)[LX], T (&us)[LX], T (&ut)[LX])
+{
+#pragma unroll
+    for (int k = 0; k < LX; ++k) s0[lidx<LX>(a, b, k)] = u[k];
+    D.mul(u, ut);
+    esync<LX>();
+    {
+        T v[LX], q[LX];
+#pragma unroll
+        for (int l = 0; l < LX; ++l) v[l] = s0[lidx<LX>(l, a, b)];   // r-pencil (j=a, k=b)
+        D.mul(v, q);
+#pragma unroll
+        for (int m = 0; m < LX; ++m) s1[lidx<LX>(m, a, b)] = q[m];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        T v[LX], q[LX];
+#pragma unroll
+        for (int l = 0; l < LX; ++l) v[l] = s0[lidx<LX>(a, l, b)];   // s-pencil (i=a, k=b)
+        D.mul(v, q);
+        esync<LX>();
+#pragma unroll
+        for (int m = 0; m < LX; ++m) s0[lidx<LX>(a, m, b)] = q[m];
+    }
+    esync<LX>();
+#pragma unroll
+    for (int k = 0; k < LX; ++k) {
+        ur[k] = s1[lidx<LX>(a, b, k)];
+        us[k] = s0[lidx<LX>(a, b, k)];
+    }
+    esync<LX>();
+}
+
+// acc = D_r^T wr + D_s^T ws + D_t^T wt, sequenced as grad_lean.  Ends synchronised.
+template <int LX, typename T, typename DS>
+__device__ __forceinline__ void div_lean(const DS &D, const T (&wr)[LX], const T (&ws)[LX],
+                                         const T (&wt)[LX], T *s0, T *s1, int a, int b, T (&acc)[LX])
+{
+#pragma unroll
+    for (int k = 0; k < LX; ++k) {
+        s0[lidx<LX>(a, b, k)] = wr[k];
+        s1[lidx<LX>(a, b, k)] = ws[k];
+    }
+    D.tmul(wt, acc);
+    esync<LX>();
+    T q[LX], q2[LX];
+    {
+        T v[LX];
+#pragma unroll
+        for (int l = 0; l < LX; ++l) v[l] = s0[lidx<LX>(l, a, b)];
+        D.tmul(v, q);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        T v[LX];
+#pragma unroll
+        for (int l = 0; l < LX; ++l) v[l] = s1[lidx<LX>(a, l, b)];
+        D.tmul(v, q2);
+    }
+    esync<LX>();
+#pragma unroll
+    for (int m = 0; m < LX; ++m) {
+        s0[lidx<LX>(m, a, b)] = q[m];
+        s1[lidx<LX>(a, m, b)] = q2[m];
+    }
+    esync<LX>();
+#pragma unroll
+    for (int k = 0; k < LX; ++k) acc[k] += s0[lidx<LX>(a, b, k)] + s1[lidx<LX>(a, b, k)];
+    esync<LX>();
+}
+
+// Four-buffer forms (A, B, C, E: one element each).  The transposes of a field pass
+// go through buffers that no lane can still be reading, which takes four workgroup
+// barriers per pass instead of eight: grad writes u to A, the r and s derivatives to B
+// and C; div writes w_r to A and w_s to E, their transposed derivatives to B and C.
+// Every buffer written after a barrier was last read before that barrier, including
+// across consecutive passes (the next pass writes B and C only after its first
+// barrier, which every lane reaches after its reads of B and C).
+template <int LX, typename T, typename DS>
+__device__ __forceinline__ void grad4(const DS &D, const T (&u)[LX], T *A, T *B, T *C, int a, int b,
+                                      T (&ur)[LX], T (&us)[LX], T (&ut)[LX])
+{
+#pragma unroll
+    for (int k = 0; k < LX; ++k) A[lidx<LX>(a, b, k)] = u[k];
+    D.mul(u, ut);
+    esync<LX>();
+    {
+        T v[LX], q[LX];
+#pragma unroll
+        for (int l = 0; l < LX; ++l) v[l] = A[lidx<LX>(l, a, b)];   // r-pencil (j=a, k=b)
+        D.mul(v, q);
+#pragma unroll
+        for (int m = 0; m < LX; ++m) B[lidx<LX>(m, a, b)] = q[m];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        T v[LX], q[LX];
+#pragma unroll
+        for (int l = 0; l < LX; ++l) v[l] = A[lidx<LX>(a, l, b)];   // s-pencil (i=a, k=b)
+        D.mul(v, q);
+#pragma unroll
+        for (int m = 0; m < LX; ++m) C[lidx<LX>(a, m, b)] = q[m];
+    }
+    esync<LX>();
+#pragma unroll
+    for (int k = 0; k < LX; ++k) {
+        ur[k] = B[lidx<LX>(a, b, k)];
+        us[k] = C[lidx<LX>(a, b, k)];
+    }
+}
+
+template <int LX, typename T, typename DS>
+__device__ __forceinline__ void div4(const DS &D, const T (&wr)[LX], const T (&ws)[LX], const T (&wt)[LX], T *A,
+                                     T *B, T *C, T *E, int a, int b, T (&acc)[LX])
+{
+#pragma unroll
+    for (int k = 0; k < LX; ++k) {
+        A[lidx<LX>(a, b, k)] = wr[k];
+        E[lidx<LX>(a, b, k)] = ws[k];
+    }
+    D.tmul(wt, acc);
+    esync<LX>();
+    {
+        T v[LX], q[LX];
+#pragma unroll
+        for (int l = 0; l < LX; ++l) v[l] = A[lidx<LX>(l, a, b)];
+        D.tmul(v, q);
+#pragma unroll
+        for (int m = 0; m < LX; ++m) B[lidx<LX>(m, a, b)] = q[m];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        T v[LX], q[LX];
+#pragma unroll
+        for (int l = 0; l < LX; ++l) v[l] = E[lidx<LX>(a, l, b)];
+        D.tmul(v, q);
+#pragma unroll
+        for (int m = 0; m < LX; ++m) C[lidx<LX>(a, m, b)] = q[m];
+    }
+    esync<LX>();
+#pragma unroll
+    for (int k = 0; k < LX; ++k) acc[k] += B[lidx<LX>(a, b, k)] + C[lidx<LX>(a, b, k)];
+}
+
+
+
+// Pencil loads and stores of the lean kernels.  eb is the element's base in one plane
+// (wave-uniform: one element per workgroup, every workgroup holds an element), t the
+// lane's column; the address is a uniform base plus a small per-lane offset, which
+// keeps per-lane 64-bit addresses out of the registers.
+template <int LX, typename T, bool NTL>
+__device__ __forceinline__ void lpencil(T (&r)[LX], const T *__restrict__ eb, unsigned t)
+{
+#pragma unroll
+    for (int k = 0; k < LX; ++k) r[k] = ldx<NTL>(eb + k * LX * LX + t);
+}
+
+template <int LX, typename T>
+__device__ __forceinline__ void spencil(T *__restrict__ eb, unsigned t, const T (&r)[LX])
+{
+#pragma unroll
+    for (int k = 0; k < LX; ++k) eb[k * LX * LX + t] = r[k];
+}
+
+// Coefficient forms of the lean kernels, fixed at compile time so that no pointer test
+// or branch sits between the loads and the arithmetic that uses them.
+enum LeanKind : int {
+    KPOISSON = 0,  // h1 scalar, no mass term
+    KHELM = 1,     // h1 scalar, h2 scalar != 0 (velocity Helmholtz)
+    KH1F = 2,      // h1 field, h2 scalar != 0
+    KGEN = 3       // anything else: h1 and h2 scalars or fields, tested at run time
+};
+
+template <typename T>
+__device__ __forceinline__ const T *ebase(const T *p, int64_t off) { return p ? p + off : nullptr; }
+
+
+// (ur, us, ut) <- h1 G (ur, us, ut) with G (and the h1 field) read in chunks of C
+// points, Ge = G + element base (plane stride n).  NTL: non-temporal loads (G used by
+// one field only).  The chunks are not requested before the gradient is done.
+template <int LX, typename T, int KIND, bool NTL>
+__device__ __forceinline__ void apply_G_lean(const T *__restrict__ Ge, const T *__restrict__ h1e, T h1s, int64_t n,
+                                             unsigned t, T (&ur)[LX], T (&us)[LX], T (&ut)[LX])
+{
+    constexpr int C = sizeof(T) == 8 ? (LX + 2) / 3 : (LX + 1) / 2;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k0 = 0; k0 < LX; k0 += C) {
+        T g[6][C], h[C];
+#pragma unroll
+        for (int kk = 0; kk < C; ++kk) {
+            if (k0 + kk < LX) {
+                const unsigned o = (k0 + kk) * (LX * LX) + t;
+#pragma unroll
+                for (int f = 0; f < 6; ++f) g[f][kk] = ldx<NTL>(Ge + f * n + o);
+                if constexpr (KIND == KH1F) h[kk] = h1e[o];
+                else if constexpr (KIND == KGEN) h[kk] = h1e ? h1e[o] : h1s;
+                else h[kk] = h1s;
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < C; ++kk) {
+            const int k = k0 + kk;
+            if (k < LX) {
+                const T r = ur[k], s = us[k], q = ut[k];
+                ur[k] = h[kk] * (g[0][kk] * r + g[3][kk] * s + g[4][kk] * q);
+                us[k] = h[kk] * (g[3][kk] * r + g[1][kk] * s + g[5][kk] * q);
+                ut[k] = h[kk] * (g[4][kk] * r + g[5][kk] * s + g[2][kk] * q);
+            }
+        }
+    }
+}
+
+// h2 B at the lane's points (zero for KPOISSON), B and the h2 field read here.
+template <int LX, typename T, int KIND>
+__device__ __forceinline__ T mass_coef(const T *__restrict__ Be, const T *__restrict__ h2e, T h2s, unsigned o)
+{
+    if constexpr (KIND == KGEN) return h2e ? h2e[o] * Be[o] : h2s * Be[o];
+    else return h2s * Be[o];
+}
+
+// w += h2 B u for u held in registers.
+template <int LX, typename T, int KIND>
+__device__ __forceinline__ void add_mass_lean(const T *__restrict__ Be, const T *__restrict__ h2e, T h2s, unsigned t,
+                                              const T (&u)[LX], T (&w)[LX])
+{
+    if constexpr (KIND != KPOISSON) {
+        if (KIND != KGEN || h2e || h2s != T(0)) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < LX; ++k) w[k] = fma(mass_coef<LX, T, KIND>(Be, h2e, h2s, k * (LX * LX) + t), u[k], w[k]);
+        }
+    }
+}
+
+// w += h2 B u with u reloaded from ue (read moments before, so served by the cache).
+template <int LX, typename T, int KIND>
+__device__ __forceinline__ void add_mass_reload(const T *__restrict__ Be, const T *__restrict__ h2e, T h2s, unsigned t,
+                                                const T *__restrict__ ue, T (&w)[LX])
+{
+    if constexpr (KIND != KPOISSON) {
+        if (KIND != KGEN || h2e || h2s != T(0)) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < LX; ++k) {
+                const unsigned o = k * (LX * LX) + t;
+                w[k] = fma(mass_coef<LX, T, KIND>(Be, h2e, h2s, o), ue[o], w[k]);
+            }
+        }
+    }
+}
+
+// (ur, us, ut) <- h1 G (ur, us, ut) from G pencils held in registers.
+template <int LX, typename T, int KIND>
+__device__ __forceinline__ void apply_G_regs(const T (&g)[6][LX], const T *__restrict__ h1e, T h1s, unsigned t,
+                                             T (&ur)[LX], T (&us)[LX], T (&ut)[LX])
+{
+#pragma unroll
+    for (int k = 0; k < LX; ++k) {
+        T h;
+        if constexpr (KIND == KH1F) h = h1e[k * (LX * LX) + t];
+        else if constexpr (KIND == KGEN) h = h1e ? h1e[k * (LX * LX) + t] : h1s;
+        else h = h1s;
+        const T r = ur[k], s = us[k], q = ut[k];
+        ur[k] = h * (g[0][k] * r + g[3][k] * s + g[4][k] * q);
+        us[k] = h * (g[3][k] * r + g[1][k] * s + g[5][k] * q);
+        ut[k] = h * (g[4][k] * r + g[5][k] * s + g[2][k] * q);
+    }
+}
+
+// The gradient and divergence halves of a field pass on NB LDS buffers.
+template <int LX, typename T, int NB, typename DS>
+__device__ __forceinline__ void grad_nb(const DS &D, const T (&u)[LX], T (*buf)[Shape<LX, T>::ESZ], int a, int b,
+                                        T (&ur)[LX], T (&us)[LX], T (&ut)[LX])
+{
+    if constexpr (NB == 4) grad4<LX, T>(D, u, buf[0], buf[1], buf[2], a, b, ur, us, ut);
+    else grad_lean<LX, T>(D, u, buf[0], buf[1], a, b, ur, us, ut);
+}
+
+template <int LX, typename T, int NB, typename DS>
+__device__ __forceinline__ void div_nb(const DS &D, const T (&wr)[LX], const T (&ws)[LX], const T (&wt)[LX],
+                                       T (*buf)[Shape<LX, T>::ESZ], int a, int b, T (&w)[LX])
+{
+    if constexpr (NB == 4) div4<LX, T>(D, wr, ws, wt, buf[0], buf[1], buf[2], buf[3], a, b, w);
+    else div_lean<LX, T>(D, wr, ws, wt, buf[0], buf[1], a, b, w);
+}
+
+// Launch configuration of the lean kernels, per precision, field count and kernel
+// (CG: the fused CG matvec, which also keeps p for its dot product).
+//  * HOLD: with three fields sharing one G, hold G's six pencils in registers (loaded
+//    once, non-temporal) instead of reading them in chunks for every field; pays for the
+//    FP32 operator up to lx = 12 (in FP64 the held pencils would cost the second wave
+//    per SIMD; the FP32 CG matvec, which also holds p, is faster reading chunks at
+//    three waves per SIMD: 4.6 -> 3.7 ms at 48^3 x lx = 12).
+//  * NB: LDS element buffers, 4 (grad4 / div4: four barriers per field pass) or 2
+//    (grad_lean / div_lean: eight); in FP64 four would halve the workgroups a compute
+//    unit holds.
+//  * MINW: waves per SIMD the register allocation is held to.
+#ifndef SEM_AX_HOLD
+#define SEM_AX_HOLD 1
+#endif
+#ifndef SEM_CG_HOLD
+#define SEM_CG_HOLD 0
+#endif
+#ifndef SEM_AX_NB32
+#define SEM_AX_NB32 4
+#endif
+#ifndef SEM_CG_NB32
+#define SEM_CG_NB32 4
+#endif
+#ifndef SEM_CG_W32H
+#define SEM_CG_W32H 3
+#endif
+template <int LX, typename T, int NF, bool CG>
+struct LeanCfg {
+    static constexpr bool F32 = sizeof(T) == 4;
+    static constexpr bool HOLD = NF > 1 && F32 && LX <= 12 && (CG ? SEM_CG_HOLD : SEM_AX_HOLD);
+    static constexpr int NB = F32 ? (CG ? SEM_CG_NB32 : SEM_AX_NB32) : 2;
+    static constexpr int MINW = HOLD ? (CG ? SEM_CG_W32H : 3)
+                                     : ((!CG && NF > 1 && !F32 && LX <= 12) ? 3 : Shape<LX, T>::MINW);
+};
+
+template <int LX, typename T, int NB>
+struct LeanBufs {
+    T buf[NB][Shape<LX, T>::ESZ];
+};
+
+// One element per workgroup; the grid holds exactly nelv workgroups.
+template <int LX, typename T, int NF, int KIND, typename DS>
+__device__ __forceinline__ void ax_lean_body(const DS &D, const AxArgs<T> &A)
+{
+    using S = Shape<LX, T>;
+    using C = LeanCfg<LX, T, NF, false>;
+    constexpr bool HOLD = C::HOLD;
+    constexpr int NB = C::NB;
+    static_assert(S::EPB == 1, "one element per workgroup");
+    __shared__ LeanBufs<LX, T, NB> lds;
+    const unsigned t = threadIdx.x;
+    const int a = t % LX, b = t / LX;
+    const int64_t e0 = (int64_t)blockIdx.x * (LX * LX * LX);
+    const T *Ge = A.G + e0;
+    const T *h1e = KIND >= KH1F ? ebase(A.h1, e0) : nullptr;
+    T g[HOLD ? 6 : 1][LX];
+    if constexpr (HOLD) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) lpencil<LX, T, true>(g[q], Ge + q * A.n, t);
+    }
+#pragma unroll 1
+    for (int f = 0; f < NF; ++f) {
+        const int64_t fe = f * A.n + e0;
+        T w[LX];
+        {
+            T ur[LX], us[LX], ut[LX];
+            {
+                T u[LX];
+                lpencil<LX, T, false>(u, A.u + fe, t);
+                grad_nb<LX, T, NB>(D, u, lds.buf, a, b, ur, us, ut);
+            }
+            if constexpr (HOLD) apply_G_regs<LX, T, KIND>(g, h1e ? fresh(h1e) : h1e, A.h1s, t, ur, us, ut);
+            else apply_G_lean<LX, T, KIND, NF == 1>(fresh(Ge), h1e ? fresh(h1e) : h1e, A.h1s, A.n, t, ur, us, ut);
+            div_nb<LX, T, NB>(D, ur, us, ut, lds.buf, a, b, w);
+        }
+        add_mass_reload<LX, T, KIND>(A.B + e0, KIND == KGEN ? ebase(A.h2, e0) : nullptr, A.h2s, t, A.u + fe, w);
+        spencil<LX, T>(A.w + fe, t, w);
+    }
+}
+
+// DMem in FP64 (the even-odd D does not fit the scalar registers), DArg in FP32.
+template <int LX, typename T, int NF, int KIND>
+__global__ SEM_BOUNDS2((Shape<LX, T>::NT), (LeanCfg<LX, T, NF, false>::MINW)) void k_ax_helm_lean(
+    AxArgs<T> A, DEo<LX, T> D, const DEo<LX, T> *__restrict__ Dg)
+{
+    if constexpr (sizeof(T) == 8) ax_lean_body<LX, T, NF, KIND>(DMem<LX, T>{Dg}, A);
+    else ax_lean_body<LX, T, NF, KIND>(DArg<LX, T>{D}, A);
+}
+
+template <int LX, typename T, int NF, int KIND, bool CG1, typename DS>
+__device__ __forceinline__ void cg_lean_body(const DS &D, const CgMatvecArgs<T> &A)
+{
+    using S = Shape<LX, T>;
+    using C = LeanCfg<LX, T, NF, true>;
+    constexpr bool HOLD = C::HOLD;
+    static_assert(S::EPB == 1 && S::NT >= 64, "one element per workgroup of at least one wave");
+    constexpr int NB = C::NB;
+    __shared__ LeanBufs<LX, T, NB> lds;
+    __shared__ double red[NF][S::NT];
+    const unsigned t = threadIdx.x;
+    const int a = t % LX, b = t / LX;
+    const int64_t e0 = (int64_t)blockIdx.x * (LX * LX * LX);
+    bool live = false;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) live = live || !A.scal[f].stop;
+    if (!live) return;
+    const T *Ge = A.G + e0;
+    const T *h1e = KIND >= KH1F ? ebase(A.h1, e0) : nullptr;
+    T g[HOLD ? 6 : 1][LX];
+    if constexpr (HOLD) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) lpencil<LX, T, true>(g[q], Ge + q * A.n, t);
+    }
+    double part[NF];
+#pragma unroll 1
+    for (int f = 0; f < NF; ++f) {
+        part[f] = 0.0;
+        const CgScalars *sc = A.scal + f;
+        if (sc->stop) continue;  // uniform
+        const int64_t fe = f * A.n + e0;
+        T p[LX];
+        {
+            T r[LX], dv[LX];
+            lpencil<LX, T, true>(r, A.r + fe, t);
+            lpencil<LX, T, NF == 1>(dv, A.dinv + e0, t);
+            if constexpr (CG1) {
+#pragma unroll
+                for (int i = 0; i < LX; ++i) p[i] = dv[i] * r[i];
+            } else {
+                const T beta = (T)sc->beta;
+                lpencil<LX, T, true>(p, A.p + fe, t);
+#pragma unroll
+                for (int i = 0; i < LX; ++i) p[i] = fma(beta, p[i], dv[i] * r[i]);
+#pragma unroll
+                for (int k = 0; k < LX; ++k) __builtin_nontemporal_store(p[k], A.p + fe + k * LX * LX + t);
+            }
+        }
+        T w[LX];
+        {
+            T ur[LX], us[LX], ut[LX];
+            grad_nb<LX, T, NB>(D, p, lds.buf, a, b, ur, us, ut);
+            if constexpr (HOLD) apply_G_regs<LX, T, KIND>(g, h1e ? fresh(h1e) : h1e, A.h1s, t, ur, us, ut);
+            else apply_G_lean<LX, T, KIND, NF == 1>(fresh(Ge), h1e ? fresh(h1e) : h1e, A.h1s, A.n, t, ur, us, ut);
+            div_nb<LX, T, NB>(D, ur, us, ut, lds.buf, a, b, w);
+        }
+        add_mass_lean<LX, T, KIND>(A.B + e0, KIND == KGEN ? ebase(A.h2, e0) : nullptr, A.h2s, t, p, w);
+        spencil<LX, T>(A.w + fe, t, w);
+        double sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < LX; ++i) sum += (double)p[i] * (double)w[i];
+        part[f] = sum;
+    }
+#pragma unroll
+    for (int q = 0; q < NF; ++q) red[q][t] = part[q];
+    __syncthreads();
+    if (t < 64) {
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            double v = 0.0;
+            for (unsigned k = t; k < S::NT; k += 64) v += red[q][k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (t == 0) A.partial[(int64_t)q * gridDim.x + blockIdx.x] = v;
+        }
+    }
+}
+
+template <int LX, typename T, int NF, int KIND, bool CG1>
+__global__ SEM_BOUNDS2((Shape<LX, T>::NT), (LeanCfg<LX, T, NF, true>::MINW)) void k_cg_matvec_lean(
+    CgMatvecArgs<T> A, DEo<LX, T> D, const DEo<LX, T> *__restrict__ Dg)
+{
+    if constexpr (sizeof(T) == 8) cg_lean_body<LX, T, NF, KIND, CG1>(DMem<LX, T>{Dg}, A);
+    else cg_lean_body<LX, T, NF, KIND, CG1>(DArg<LX, T>{D}, A);
+}
+
+// g = (D v)^T G (D u) per point, lean form: G (D u) is formed first (G read in
+// chunks), then the gradient of v is taken and contracted with it.
+template <int LX, typename T, typename DS>
+__device__ __forceinline__ void adj_lean_body(const DS &D, const AdjArgs<T> &A)
+{
+    using S = Shape<LX, T>;
+    static_assert(S::EPB == 1, "one element per workgroup");
+    __shared__ Lds<LX, T> lds;
+    const unsigned t = threadIdx.x;
+    const int a = t % LX, b = t / LX;
+    const int64_t e0 = (int64_t)blockIdx.x * (LX * LX * LX);
+    T *s0 = lds.buf[0][0], *s1 = lds.buf[1][0];
+    T wr[LX], ws[LX], wt[LX];
+    {
+        T u[LX];
+        lpencil<LX, T, false>(u, A.u + e0, t);
+        grad_lean<LX, T>(D, u, s0, s1, a, b, wr, ws, wt);
+    }
+    apply_G_lean<LX, T, KPOISSON, true>(fresh(A.G + e0), (const T *)nullptr, T(1), A.n, t, wr, ws, wt);
+    T vr[LX], vs[LX], vt[LX];
+    {
+        T v[LX];
+        lpencil<LX, T, false>(v, A.v + e0, t);
+        grad_lean<LX, T>(D, v, s0, s1, a, b, vr, vs, vt);
+    }
+    T out[LX];
+#pragma unroll
+    for (int i = 0; i < LX; ++i) out[i] = vr[i] * wr[i] + vs[i] * ws[i] + vt[i] * wt[i];
+    spencil<LX, T>(A.g + e0, t, out);
+}
+
+template <int LX, typename T>
+__global__ SEM_BOUNDS2((Shape<LX, T>::NT), (Shape<LX, T>::MINW)) void k_ax_adjoint_lean(
+    AdjArgs<T> A, DEo<LX, T> D, const DEo<LX, T> *__restrict__ Dg)
+{
+    if constexpr (sizeof(T) == 8) adj_lean_body<LX, T>(DMem<LX, T>{Dg}, A);
+    else adj_lean_body<LX, T>(DArg<LX, T>{D}, A);
 }
 
 // ------------------------------------------------------------------ Schwarz local solves
@@ -628,7 +1253,7 @@ __global__ __launch_bounds__(ProlongShape<LX>::NT) void k_prolong(ProlongArgs A)
 // ------------------------------------------------------------------ h1-adjoint
 // g = (D v)^T G (D u) per point.
 template <int LX, typename T>
-__global__ SEM_BOUNDS((Shape<LX, T>::NT)) void k_ax_adjoint(AdjArgs<T> A, DEo<LX, T> D)
+__global__ SEM_BOUNDS2((Shape<LX, T>::NT), (Shape<LX, T>::MINW)) void k_ax_adjoint(AdjArgs<T> A, DEo<LX, T> D)
 {
     using S = Shape<LX, T>;
     __shared__ Lds<LX, T> lds;
@@ -784,6 +1409,15 @@ sem::DEo<LX, T> make_deo(const double *D)
     return m;
 }
 
+// Coefficient form of a lean launch (see LeanKind).
+template <typename T>
+int lean_kind(const T *h1, const T *h2, T h2s)
+{
+    if (h2) return sem::KGEN;
+    if (h2s == T(0)) return h1 ? sem::KGEN : sem::KPOISSON;
+    return h1 ? sem::KH1F : sem::KHELM;
+}
+
 template <typename T>
 hipError_t launch_ax(const sem::AxArgs<T> &A, const double *D, int nfields, hipStream_t st)
 {
@@ -791,14 +1425,37 @@ hipError_t launch_ax(const sem::AxArgs<T> &A, const double *D, int nfields, hipS
     const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
     if (grid == 0) return hipSuccess;
     const auto Dm = make_deo<SEM_LX, T>(D);
-    const bool gen = A.h1 || A.h2 || A.h2s != T(0);
-    const unsigned pad = 0;
-    if (nfields == 3) {
-        if (gen) hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 3, true>), dim3(grid), dim3(S::NT), pad, st, A, Dm);
-        else hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 3, false>), dim3(grid), dim3(S::NT), pad, st, A, Dm);
+    if constexpr (S::LEAN) {
+        if (sizeof(T) == 8 && !A.deo) return hipErrorInvalidValue;
+        const int kind = lean_kind(A.h1, A.h2, A.h2s);
+#define SEM_LEAN_AX(NF_, K_)                                                                               \
+    hipLaunchKernelGGL((sem::k_ax_helm_lean<SEM_LX, T, NF_, K_>), dim3(grid), dim3(S::NT), 0, st, A, Dm, \
+                       (const sem::DEo<SEM_LX, T> *)A.deo)
+        if (nfields == 3) {
+            switch (kind) {
+            case sem::KPOISSON: SEM_LEAN_AX(3, sem::KPOISSON); break;
+            case sem::KHELM: SEM_LEAN_AX(3, sem::KHELM); break;
+            case sem::KH1F: SEM_LEAN_AX(3, sem::KH1F); break;
+            default: SEM_LEAN_AX(3, sem::KGEN); break;
+            }
+        } else {
+            switch (kind) {
+            case sem::KPOISSON: SEM_LEAN_AX(1, sem::KPOISSON); break;
+            case sem::KHELM: SEM_LEAN_AX(1, sem::KHELM); break;
+            case sem::KH1F: SEM_LEAN_AX(1, sem::KH1F); break;
+            default: SEM_LEAN_AX(1, sem::KGEN); break;
+            }
+        }
+#undef SEM_LEAN_AX
     } else {
-        if (gen) hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 1, true>), dim3(grid), dim3(S::NT), pad, st, A, Dm);
-        else hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 1, false>), dim3(grid), dim3(S::NT), pad, st, A, Dm);
+        const bool gen = A.h1 || A.h2 || A.h2s != T(0);
+        if (nfields == 3) {
+            if (gen) hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 3, true>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+            else hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 3, false>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+        } else {
+            if (gen) hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 1, true>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+            else hipLaunchKernelGGL((sem::k_ax_helm<SEM_LX, T, 1, false>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+        }
     }
     return hipGetLastError();
 }
@@ -810,13 +1467,37 @@ hipError_t launch_cg(const sem::CgMatvecArgs<T> &A, const double *D, int nfields
     const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
     if (grid == 0) return hipSuccess;
     const auto Dm = make_deo<SEM_LX, T>(D);
-    const bool gen = A.h1 || A.h2 || A.h2s != T(0);
-    if (nfields == 3) {
-        if (gen) hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3, true, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
-        else hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3, false, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+    if constexpr (S::LEAN) {
+        if (sizeof(T) == 8 && !A.deo) return hipErrorInvalidValue;
+        const int kind = lean_kind(A.h1, A.h2, A.h2s);
+#define SEM_LEAN_CG(NF_, K_)                                                                               \
+    hipLaunchKernelGGL((sem::k_cg_matvec_lean<SEM_LX, T, NF_, K_, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm, \
+                       (const sem::DEo<SEM_LX, T> *)A.deo)
+        if (nfields == 3) {
+            switch (kind) {
+            case sem::KPOISSON: SEM_LEAN_CG(3, sem::KPOISSON); break;
+            case sem::KHELM: SEM_LEAN_CG(3, sem::KHELM); break;
+            case sem::KH1F: SEM_LEAN_CG(3, sem::KH1F); break;
+            default: SEM_LEAN_CG(3, sem::KGEN); break;
+            }
+        } else {
+            switch (kind) {
+            case sem::KPOISSON: SEM_LEAN_CG(1, sem::KPOISSON); break;
+            case sem::KHELM: SEM_LEAN_CG(1, sem::KHELM); break;
+            case sem::KH1F: SEM_LEAN_CG(1, sem::KH1F); break;
+            default: SEM_LEAN_CG(1, sem::KGEN); break;
+            }
+        }
+#undef SEM_LEAN_CG
     } else {
-        if (gen) hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1, true, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
-        else hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1, false, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+        const bool gen = A.h1 || A.h2 || A.h2s != T(0);
+        if (nfields == 3) {
+            if (gen) hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3, true, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+            else hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 3, false, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+        } else {
+            if (gen) hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1, true, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+            else hipLaunchKernelGGL((sem::k_cg_matvec<SEM_LX, T, 1, false, CG1>), dim3(grid), dim3(S::NT), 0, st, A, Dm);
+        }
     }
     return hipGetLastError();
 }
@@ -827,8 +1508,14 @@ hipError_t launch_adj(const sem::AdjArgs<T> &A, const double *D, hipStream_t st)
     using S = sem::Shape<SEM_LX, T>;
     const unsigned grid = (unsigned)((A.nelv + S::EPB - 1) / S::EPB);
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((sem::k_ax_adjoint<SEM_LX, T>), dim3(grid), dim3(S::NT), 0, st, A,
-                       make_deo<SEM_LX, T>(D));
+    if constexpr (S::LEAN) {
+        if (sizeof(T) == 8 && !A.deo) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((sem::k_ax_adjoint_lean<SEM_LX, T>), dim3(grid), dim3(S::NT), 0, st, A,
+                           make_deo<SEM_LX, T>(D), (const sem::DEo<SEM_LX, T> *)A.deo);
+    }
+    else
+        hipLaunchKernelGGL((sem::k_ax_adjoint<SEM_LX, T>), dim3(grid), dim3(S::NT), 0, st, A,
+                           make_deo<SEM_LX, T>(D));
     return hipGetLastError();
 }
 }  // namespace
@@ -906,6 +1593,15 @@ hipError_t SEM_PASTE(sem_launch_diag_lx, SEM_LX)(const sem::DiagArgs *A, const d
     hipLaunchKernelGGL((sem::k_diag<SEM_LX>), dim3(grid), dim3(256), 0, st, *A,
                        make_dmat<SEM_LX, double>(D));
     return hipGetLastError();
+}
+// The even-odd D of this lx in FP64 and FP32 (the DEo layouts), for the device copy
+// the lean FP64 kernels read (out64, out32: host buffers of the two struct sizes).
+void SEM_PASTE(sem_deo_fill_lx, SEM_LX)(const double *D, void *out64, void *out32)
+{
+    const auto m64 = make_deo<SEM_LX, double>(D);
+    const auto m32 = make_deo<SEM_LX, float>(D);
+    memcpy(out64, &m64, sizeof(m64));
+    memcpy(out32, &m32, sizeof(m32));
 }
 // number of per-workgroup partials the CG matvec writes per field
 int64_t SEM_PASTE(sem_cg_nblocks_f64_lx, SEM_LX)(int64_t nelv)

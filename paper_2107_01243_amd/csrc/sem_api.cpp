@@ -19,7 +19,7 @@ const LxFns &fns(int lx)
     {sem_launch_ax_f64_lx##L, sem_launch_ax_f32_lx##L, sem_launch_cg_f64_lx##L, sem_launch_cg_f32_lx##L, \
      sem_launch_cg1_f64_lx##L, sem_launch_fdm_lx##L, sem_launch_prolong_lx##L,                     \
      sem_launch_adj_f64_lx##L, sem_launch_adj_f32_lx##L, sem_launch_geom_lx##L, sem_launch_diag_lx##L,  \
-     sem_cg_nblocks_f64_lx##L, sem_cg_nblocks_f32_lx##L},
+     sem_cg_nblocks_f64_lx##L, sem_cg_nblocks_f32_lx##L, sem_deo_fill_lx##L},
     static const LxFns table[] = {SEM_LX_LIST(SEM_ROW)};
     return table[lx - SEM_LX_MIN];
 }
@@ -90,11 +90,16 @@ sem_status gs_upload(sem_gs g)
     const std::vector<int32_t> pairs, &blk_idx = m.big_idx;
     const std::vector<int64_t> &blk_ptr = m.big_ptr;
     g->entries = true;
-    SEM_TRY(dalloc(&g->d_ent_idx, m.ent_idx.size()));
-    SEM_TRY(dalloc(&g->d_ent_meta, m.ent_meta.size()));
-    if (!m.ent_idx.empty()) {
-        HIP_TRY(hipMemcpy(g->d_ent_idx, m.ent_idx.data(), m.ent_idx.size() * 4, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(g->d_ent_meta, m.ent_meta.data(), m.ent_meta.size() * 2, hipMemcpyHostToDevice));
+    // one word per entry: the local index with bit 31 marking a group's first entry
+    // (the kernel recovers positions and group sizes from these flags), padding all ones
+    {
+        std::vector<uint32_t> word(m.ent_idx.size());
+        for (size_t q = 0; q < word.size(); ++q)
+            word[q] = m.ent_idx[q] < 0 ? 0xffffffffu
+                                       : ((uint32_t)m.ent_idx[q] | ((m.ent_meta[q] & 0xffu) == 0 ? 0x80000000u : 0u));
+        SEM_TRY(dalloc(&g->d_ent_word, word.size()));
+        if (!word.empty())
+            HIP_TRY(hipMemcpy(g->d_ent_word, word.data(), word.size() * 4, hipMemcpyHostToDevice));
     }
 #elif SEM_GS_ELEMENT_ORDER
     std::vector<int32_t> pairs, blk_idx;
@@ -403,8 +408,7 @@ void sem_gs_destroy(sem_gs gs)
     dfree(gs->d_blk_ptr);
     dfree(gs->d_blk_idx);
     dfree(gs->d_owner);
-    dfree(gs->d_ent_idx);
-    dfree(gs->d_ent_meta);
+    dfree(gs->d_ent_word);
     delete gs;
 }
 
@@ -453,6 +457,20 @@ static sem_status coef_alloc(sem_space Xh, sem_mesh msh, unsigned flags, sem_coe
     if ((s = dalloc(&c->G, 6 * c->n)) != SEM_OK || (s = dalloc(&c->B, c->n)) != SEM_OK) {
         sem_coef_destroy(c);
         return s;
+    }
+    {
+        // the even-odd D of this lx in device memory (read by the kernels for lx >= 10)
+        constexpr size_t b64 = sizeof(DEo<SEM_LX_MAX, double>), b32 = sizeof(DEo<SEM_LX_MAX, float>);
+        unsigned char h64[b64] = {}, h32[b32] = {};
+        fns(c->lx).deo(Xh->D, h64, h32);
+        hipError_t e = hipSuccess;
+        if ((s = dalloc((unsigned char **)&c->deo64, b64)) != SEM_OK ||
+            (s = dalloc((unsigned char **)&c->deo32, b32)) != SEM_OK ||
+            (e = hipMemcpy(c->deo64, h64, b64, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c->deo32, h32, b32, hipMemcpyHostToDevice)) != hipSuccess) {
+            sem_coef_destroy(c);
+            return s != SEM_OK ? s : fail(SEM_ERR_HIP, "upload of D failed: %s", hipGetErrorString(e));
+        }
     }
     if (flags & SEM_COEF_F32) {
         if ((s = dalloc(&c->G32, 6 * c->n)) != SEM_OK || (s = dalloc(&c->B32, c->n)) != SEM_OK) {
@@ -583,7 +601,7 @@ void sem_coef_destroy(sem_coef c)
     c->sz.release();
     dfree(c->G); dfree(c->B); dfree(c->G32); dfree(c->B32);
     dfree(c->h1); dfree(c->h2); dfree(c->h1_32); dfree(c->h2_32);
-    dfree(c->dinv); dfree(c->dinv32);
+    dfree(c->dinv); dfree(c->dinv32); dfree(c->deo64); dfree(c->deo32);
     delete c;
 }
 
@@ -615,10 +633,12 @@ sem_status sem_ax_helm_adjoint(void *g, const void *u, const void *v, sem_coef c
     if (overlap(g, bytes, u, bytes) || overlap(g, bytes, v, bytes)) return fail(SEM_ERR_INVALID, "g overlaps u or v");
     hipError_t e;
     if (dt == SEM_F64) {
-        AdjArgs<double> A{(double *)g, (const double *)u, (const double *)v, coef->G, coef->n, coef->nelv};
+        AdjArgs<double> A{(double *)g, (const double *)u, (const double *)v, coef->G, coef->n, coef->nelv,
+                          coef->deo64};
         e = fns(coef->lx).adj64(&A, Xh->D, S(stream));
     } else {
-        AdjArgs<float> A{(float *)g, (const float *)u, (const float *)v, coef->G32, coef->n, coef->nelv};
+        AdjArgs<float> A{(float *)g, (const float *)u, (const float *)v, coef->G32, coef->n, coef->nelv,
+                         coef->deo32};
         e = fns(coef->lx).adj32(&A, Xh->D, S(stream));
     }
     HIP_TRY(e);

@@ -78,6 +78,7 @@ sem_status cg_iterate(sem_coef c, Work &W, sem_gs g, int nf, T *x, T *r, T *p, T
     M.nelv = c->nelv;
     M.scal = W.scal;
     M.partial = W.partial;
+    M.deo = sizeof(T) == 8 ? c->deo64 : c->deo32;
     CgUpdateArgs<T> U{x, r, p, w, dinv, g->d_owner, W.scal, W.partial, n, nf};
     CgFinishArgs F{W.partial, (int64_t)ug, W.scal, hist, hist_len, nf};
     if (check_every < 1) check_every = 1;
@@ -256,6 +257,7 @@ static sem_status pcg_cg1(double *x, const double *b, int nf, sem_coef c, sem_gs
     M.nelv = c->nelv;
     M.scal = W.scal;
     M.partial = W.partial;
+    M.deo = c->deo64;
     // the update's partials go where the fold job reads them (see ensure_work)
     const Cg1UpdateArgs U{x, W.r, W.p, W.s, W.w, c->dinv, g->d_owner, W.scal, W.partial + 3 * W.nb, n, nf};
     auto prime = [&]() -> sem_status {  // matvec of the current r and the first fold
@@ -388,11 +390,17 @@ static sem_status pcg_mixed_reliable(double *x, const double *b, int nf, sem_coe
     M.nelv = c->nelv;
     M.scal = W.scal;
     M.partial = W.partial;
+    M.deo = c->deo32;
     CgUpdateArgs<float> U{W.y32, W.r32, W.p32, W.w32, c->dinv32, g->d_owner, W.scal, W.partial, n, nf};
     const unsigned ug = sem_update_grid(n, 1);
     CgFinishArgs F{W.partial, (int64_t)ug, W.scal, nullptr, 0, nf};
     const int check_every = std::max(1, P->check_every);
-    const int64_t max_polls = (int64_t)P->max_iter / check_every + 64 * 64;
+    const int64_t max_polls = (int64_t)P->max_iter + 64 * 64;  // every poll runs >= 1 iteration or ends a segment
+    // Launches queued between polls after a segment has ended do no work but still
+    // cost a pass over the vectors, so the next poll is placed where the current
+    // segment is expected to end: at the length of the previous segment (check_every
+    // before any has ended, check_every / 4 once the estimate is passed).
+    int seg_len[3] = {0, 0, 0}, seg_start[3] = {0, 0, 0};
     for (int64_t poll = 0; poll < max_polls; ++poll) {
         HIP_TRY(hipMemcpyAsync(W.h_scal, W.scal, sizeof(CgScalars) * nf, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(W.h_rel, W.rel, sizeof(RelState) * nf, hipMemcpyDeviceToHost, st));
@@ -401,6 +409,10 @@ static sem_status pcg_mixed_reliable(double *x, const double *b, int nf, sem_coe
         for (int f = 0; f < nf; ++f) {
             all_stopped = all_stopped && W.h_scal[f].stop;
             all_done = all_done && W.h_rel[f].done;
+            if (W.h_rel[f].last_iter != seg_start[f]) {
+                seg_len[f] = W.h_rel[f].last_iter - seg_start[f];
+                seg_start[f] = W.h_rel[f].last_iter;
+            }
         }
         if (all_done) break;
         if (all_stopped) {
@@ -415,7 +427,13 @@ static sem_status pcg_mixed_reliable(double *x, const double *b, int nf, sem_coe
             HIP_TRY(sem_launch_rel_resume(&RF, W.rel, 0, st));
             continue;
         }
-        for (int it = 0; it < check_every; ++it) {
+        int todo = check_every;
+        for (int f = 0; f < nf; ++f) {
+            if (W.h_rel[f].done || W.h_scal[f].stop || seg_len[f] <= 0) continue;
+            const int rem = seg_len[f] - (W.h_scal[f].iter - seg_start[f]);
+            todo = std::min(todo, rem > 0 ? rem : std::max(1, check_every / 4));
+        }
+        for (int it = 0; it < todo; ++it) {
             HIP_TRY(fns(c->lx).cg32(&M, c->Xh->D, nf, st));
             SEM_TRY(launch_gs<float>(W.w32, nf, g, W.scal, W.job32, st));
             HIP_TRY(sem_launch_cg_update_f32(&U, ug, st));

@@ -50,7 +50,8 @@ using namespace sem;
                                                 hipStream_t);                                               \
     extern "C" hipError_t sem_launch_diag_lx##L(const DiagArgs *, const double *, hipStream_t);             \
     extern "C" int64_t sem_cg_nblocks_f64_lx##L(int64_t);                                                   \
-    extern "C" int64_t sem_cg_nblocks_f32_lx##L(int64_t);
+    extern "C" int64_t sem_cg_nblocks_f32_lx##L(int64_t);                                                   \
+    extern "C" void sem_deo_fill_lx##L(const double *, void *, void *);
 SEM_LX_LIST(SEM_DECL)
 
 extern "C" {
@@ -117,6 +118,7 @@ struct LxFns {
     hipError_t (*diag)(const DiagArgs *, const double *, hipStream_t);
     int64_t (*nblk64)(int64_t);
     int64_t (*nblk32)(int64_t);
+    void (*deo)(const double *, void *, void *);
 };
 
 // launchers of the kernels instantiated for one lx
@@ -195,8 +197,7 @@ struct sem_gs_s {
     int64_t *d_blk_ptr = nullptr;
     int32_t *d_blk_idx = nullptr;
     uint8_t *d_owner = nullptr;
-    int32_t *d_ent_idx = nullptr;
-    uint16_t *d_ent_meta = nullptr;
+    uint32_t *d_ent_word = nullptr;  // entry-parallel list, one packed word per entry
     bool entries = false;  // entry-parallel execution (groups > 64 copies via d_blk_*)
     int64_t npairs() const { return (int64_t)m.pairs.size() / 2; }
     int64_t nblocks() const { return (int64_t)m.blk_ptr.size() - 1; }
@@ -306,6 +307,7 @@ struct sem_coef_s {
     float *h1_32 = nullptr, *h2_32 = nullptr;
     double *dinv = nullptr;
     float *dinv32 = nullptr;
+    void *deo64 = nullptr, *deo32 = nullptr;  // device copies of the even-odd D (FP64, FP32)
     bool dinv_valid = false;
     const void *dinv_gs = nullptr;
     semi::Work ws;
@@ -333,8 +335,7 @@ sem_status launch_gs(T *u, int nf, sem_gs g, const CgScalars *skip, const AlphaJ
     A.nfields = nf;
     A.skip = skip;
     A.alpha_job = job;
-    A.ent_idx = g->d_ent_idx;
-    A.ent_meta = g->d_ent_meta;
+    A.ent_word = g->d_ent_word;
     A.nent = g->entries ? (int64_t)g->m.ent_idx.size() : 0;
     A.max_group = g->m.max_group;
     if (A.npairs + A.nblocks + A.nent == 0 && job == nullptr) return SEM_OK;
@@ -356,10 +357,12 @@ sem_status launch_ax(sem_coef c, T *w, const T *u, int nf, hipStream_t st)
     hipError_t e;
     if constexpr (sizeof(T) == 8) {
         A.G = c->G; A.B = c->B; A.h1 = c->h1; A.h2 = c->h2; A.h1s = c->h1s; A.h2s = c->h2s;
+        A.deo = c->deo64;
         e = fns(c->lx).ax64(&A, c->Xh->D, nf, st);
     } else {
         A.G = c->G32; A.B = c->B32; A.h1 = c->h1_32; A.h2 = c->h2_32;
         A.h1s = (float)c->h1s; A.h2s = (float)c->h2s;
+        A.deo = c->deo32;
         e = fns(c->lx).ax32(&A, c->Xh->D, nf, st);
     }
     HIP_TRY(e);

@@ -50,6 +50,7 @@ struct AxArgs {
     T h1s, h2s;
     int64_t n;    // points per field
     int64_t nelv;
+    const void *deo = nullptr;  // device copy of the even-odd D of this lx and precision
 };
 
 // Per-field scalars of one CG solve, resident in device memory.
@@ -84,6 +85,7 @@ struct CgMatvecArgs {
     int64_t nelv;
     const CgScalars *scal;  // one per field
     double *partial;        // [field][workgroup]
+    const void *deo = nullptr;  // device copy of the even-odd D of this lx and precision
 };
 
 template <typename T>
@@ -94,6 +96,7 @@ struct AdjArgs {
     const T *G;
     int64_t n;
     int64_t nelv;
+    const void *deo = nullptr;  // device copy of the even-odd D of this lx and precision
 };
 
 struct GeomArgs {

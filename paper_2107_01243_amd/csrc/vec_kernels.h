@@ -52,8 +52,9 @@ struct GsArgs {
     const AlphaJob *alpha_job;  // optional (device pointer)
     // entry-parallel form (used when nent > 0; pairs/blocks then hold only groups
     // with more than 64 copies)
-    const int32_t *ent_idx;
-    const uint16_t *ent_meta;
+    // one word per entry: the local index, bit 31 set on the first entry of a group;
+    // 0xffffffff pads a 64-entry segment (no group straddles a segment)
+    const uint32_t *ent_word;
     int64_t nent;
     int max_group;
 };

@@ -219,14 +219,20 @@ __global__ __launch_bounds__(VT) void k_gs_entries(GsArgs<T> A)
     const int64_t base = ((int64_t)lb * VT + (int64_t)wave * 64) * GEPL + lane;
     int32_t e[GEPL];
     int cnt[GEPL], lead[GEPL];
+    // a group's extent from the start flags of the segment: its first lane is the
+    // nearest flagged lane at or below this one, its end the next flagged lane (padding
+    // counts as flagged, and every segment opens with a flagged lane)
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
 #pragma unroll
     for (int k = 0; k < GEPL; ++k) {
         const int64_t t = base + 64 * k;
-        const bool in = t < A.nent;
-        e[k] = in ? A.ent_idx[t] : -1;
-        const unsigned meta = in ? A.ent_meta[t] : 0u;
-        cnt[k] = (int)(meta >> 8);
-        lead[k] = lane - (int)(meta & 0xffu);
+        const uint32_t wd = t < A.nent ? A.ent_word[t] : 0xffffffffu;
+        const bool pad = wd == 0xffffffffu;
+        e[k] = pad ? -1 : (int32_t)(wd & 0x7fffffffu);
+        const uint64_t M = __ballot(pad || (wd >> 31) != 0);
+        lead[k] = 63 - __clzll((long long)(M & upto));
+        const uint64_t above = M & ~upto;
+        cnt[k] = (above ? __ffsll((long long)above) - 1 : 64) - lead[k];
     }
     for (int f = 0; f < A.nfields; ++f) {
         if (A.skip && A.skip[f].stop) continue;

@@ -42,3 +42,43 @@ def test_profiled_traffic_sums_fetch_and_write_when_sources_match(monkeypatch, t
     monkeypatch.setattr(bench, "PROFILE_MD", str(md))
     assert bench.profiled_traffic("k") == 1024
     assert bench.profiled_traffic("other") is None
+
+
+def _write_csv(path, header, rows):
+    import csv
+    with open(path, "w", newline="") as fh:
+        wr = csv.writer(fh)
+        wr.writerow(header)
+        wr.writerows(rows)
+
+
+def test_profile_summary_scales_counters_by_the_copy(monkeypatch, tmp_path):
+    """summarize_profile: per-launch means of FETCH_SIZE / WRITE_SIZE (KiB) scaled so that
+    the largest plain device copy reads 1 GiB each way; the written block is what
+    profiled_traffic reads back."""
+    for d in ("trace", "fetch", "write"):
+        (tmp_path / d).mkdir()
+    _write_csv(tmp_path / "trace" / "x_kernel_stats.csv", ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"],
+               [["void sem::k_ax_helm<8, double, 1, false>(sem::AxArgs<double>, sem::DEo<8, double>)", 2, 400000,
+                 200000, 60.0],
+                ["__amd_rocclr_copyBuffer", 1, 300000, 300000, 40.0]])
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value", "Grid_Size"]
+    _write_csv(tmp_path / "fetch" / "x_counter_collection.csv", hdr,
+               [["void sem::k_ax_helm<8, double, 1, false>(sem::AxArgs<double>, sem::DEo<8, double>)", "FETCH_SIZE",
+                 1000.0, 4096],
+                ["void sem::k_ax_helm<8, double, 1, false>(sem::AxArgs<double>, sem::DEo<8, double>)", "FETCH_SIZE",
+                 3000.0, 4096],
+                ["__amd_rocclr_copyBuffer", "FETCH_SIZE", 524288.0, 131072],
+                ["__amd_rocclr_copyBuffer", "FETCH_SIZE", 10.0, 64]])
+    _write_csv(tmp_path / "write" / "x_counter_collection.csv", hdr,
+               [["void sem::k_ax_helm<8, double, 1, false>(sem::AxArgs<double>, sem::DEo<8, double>)", "WRITE_SIZE",
+                 500.0, 4096],
+                ["__amd_rocclr_copyBuffer", "WRITE_SIZE", 1048576.0, 131072]])
+    out = tmp_path / "s.md"
+    bench.summarize_profile(str(tmp_path / "trace"), str(tmp_path / "fetch"), str(tmp_path / "write"), str(out),
+                            "test", "workload", ["cmd"], ["bench.py"])
+    monkeypatch.setattr(bench, "PROFILE_MD", str(out))
+    # fetch: mean 2000 KiB x 2 (the copy read 512 MiB for 1 GiB moved); write: 500 KiB x 1
+    assert bench.profiled_traffic("sem::k_ax_helm<8, double, 1, false>") == 2000 * 1024 * 2 + 500 * 1024
+    text = out.read_text()
+    assert "| `sem::k_ax_helm<8, double, 1, false>` | 2 | 200.00 |" in text
