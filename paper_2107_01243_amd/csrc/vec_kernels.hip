@@ -834,6 +834,11 @@ __global__ __launch_bounds__(VT) void k_cg_update(CgUpdateArgs<T> A)
         // last point, so every load is in bounds and unconditional; those lanes store
         // and accumulate nothing).  Measured: 79 -> 67 us at 16.8M points.  (In FP64
         // the same form was slower.)
+        // With several fields, launches queued after a field has stopped (its segment
+        // ended between host polls) are frequent and each would still read every operand
+        // of that field: there the flag is tested first (it costs one scalar-load latency
+        // per workgroup, negligible against a multi-field chunk).
+        if (A.nfields > 1 && A.scal[f].stop) return;
         const int stop = A.scal[f].stop;
         const T alpha = (T)A.scal[f].alpha;
         const int64_t t0 = (int64_t)blockIdx.x * UV * VT + threadIdx.x;
