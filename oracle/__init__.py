@@ -335,7 +335,7 @@ class Problem:
         return x0, b - self.apply(x0)
 
     # -------------------------------------------------------------- two-level Schwarz
-    def schwarz_setup(self, extend=True):
+    def schwarz_setup(self, extend=True, overlap=False):
         """Data of the two-level additive overlapping Schwarz preconditioner of the
         pressure solve (Section 4: M^{-1} = R0^T A0^{-1} R0 + sum_k Rk^T Ak~^{-1} Rk;
         coarse grid on linear elements).  Local problem k: element k's lx^3 points with
@@ -345,37 +345,81 @@ class Problem:
         L = 2 / sqrt(mean over the element of G_dd / B) plus one linear segment of the
         first-spacing length at each end (extend=False drops the segments: the element
         alone, for checks).  Coarse space: trilinear functions of the element vertices;
-        A0 = P^T A P (Galerkin) on the free vertices.  h1, h2 scalars."""
+        A0 = P^T A P (Galerkin) on the free vertices.  h1, h2 scalars.
+
+        overlap=True: the minimal overlap of one point.  Beyond every face that element k
+        shares with a neighbour, the local problem also holds the layer of the
+        neighbour's points one GLL index inside it: along that direction the 1-D
+        operator gains a free extension node, joined to the face point by the
+        first-spacing segment and held by a Dirichlet condition one second-GLL-spacing
+        (J (xi_2 - xi_1)) beyond it; faces without a neighbour keep the extend=True
+        segment.  The local right-hand side is the residual on the element's points and,
+        on the extension layers, the neighbour's residual; the box's edge and corner
+        points (outside the element in two or three directions) get zero.
+        schwarz_apply then keeps each local solution on the element's own points only
+        (restricted additive Schwarz) before the sum over shared points."""
         if not (np.isscalar(self.h1) and np.isscalar(self.h2)):
             raise ValueError("the Schwarz preconditioner takes scalar h1, h2")
         lx, N, E = self.lx, self.lx - 1, self.nelv
         xi, w, D = self.xi, self.w, self.D
         Kref = D.T @ np.diag(w) @ D          # 1-D stiffness on [-1, 1]
         dref = xi[1] - xi[0]                 # first GLL spacing on [-1, 1]
+        dref2 = xi[min(2, N)] - xi[min(2, N) - 1]  # second spacing (the first when lx = 2)
         G = np.asarray(self.G).reshape(6, E, lx ** 3)
         B = np.asarray(self.B).reshape(E, lx ** 3)
+        self._overlap = bool(overlap)
+        src = self._extension_sources() if overlap else None
         self._loc = []
+        self._ov = []
         for e in range(E):
-            Ks, Ms = [], []
+            Ks, Ms, ranges = [], [], []
             for d in range(3):
                 L = 2.0 / np.sqrt(np.mean(G[d, e] / B[e]))
                 J = L / 2.0
-                K = Kref / J
-                M = np.diag(w * J)
-                if extend:
-                    h = J * dref             # length of each extension segment
-                    K[0, 0] += 1.0 / h
-                    K[N, N] += 1.0 / h
-                    M[0, 0] += h / 2.0
-                    M[N, N] += h / 2.0
+                h, h2 = J * dref, J * dref2  # extension segment, and the one beyond
+                lo = bool(overlap) and src[e][2 * d] is not None
+                hi = bool(overlap) and src[e][2 * d + 1] is not None
+                o = int(lo)
+                nd = lx + int(lo) + int(hi)
+                K = np.zeros((nd, nd))
+                M = np.zeros((nd, nd))
+                K[o:o + lx, o:o + lx] = Kref / J
+                M[o:o + lx, o:o + lx] = np.diag(w * J)
+                for has, f, xn in ((lo, o, o - 1), (hi, o + N, o + N + 1)):
+                    if has:
+                        K[np.ix_([xn, f], [xn, f])] += np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
+                        M[xn, xn] += h / 2.0 + h2 / 2.0
+                        M[f, f] += h / 2.0
+                        K[xn, xn] += 1.0 / h2
+                    elif extend:
+                        K[f, f] += 1.0 / h
+                        M[f, f] += h / 2.0
                 Ks.append(K)
                 Ms.append(M)
+                ranges.append(np.arange(-int(lo), lx + int(hi)))
             # point (i, j, k) at i + lx j + lx^2 k: kron(t, s, r)
             Kr, Ksd, Kt = Ks
             Mr, Msd, Mt = Ms
             A = self.h1 * (np.kron(Mt, np.kron(Msd, Kr)) + np.kron(Mt, np.kron(Ksd, Mr)) +
                            np.kron(Kt, np.kron(Msd, Mr))) + self.h2 * np.kron(Mt, np.kron(Msd, Mr))
             self._loc.append(A)
+            if overlap:
+                # box points (I, J, K), I fastest: where each takes its right-hand side
+                I = np.tile(ranges[0], len(ranges[1]) * len(ranges[2]))
+                Jc = np.tile(np.repeat(ranges[1], len(ranges[0])), len(ranges[2]))
+                Kc = np.repeat(ranges[2], len(ranges[0]) * len(ranges[1]))
+                out = [(c < 0) | (c > N) for c in (I, Jc, Kc)]
+                nout = out[0].astype(int) + out[1] + out[2]
+                own = nout == 0
+                gather = np.full(I.size, -1, dtype=np.int64)
+                gather[own] = e * lx ** 3 + (I + lx * (Jc + lx * Kc))[own]
+                for q in np.flatnonzero(nout == 1):
+                    c = [I[q], Jc[q], Kc[q]]
+                    d = [out[0][q], out[1][q], out[2][q]].index(True)
+                    side = int(c[d] > N)
+                    c[d] = N if side else 0
+                    gather[q] = src[e][2 * d + side][c[0] + lx * (c[1] + lx * c[2])]
+                self._ov.append((np.linalg.inv(A), gather, own))
         # coarse space: vertices = global ids of the element corners
         corner = [i + lx * (j + lx * k) for k in (0, N) for j in (0, N) for i in (0, N)]
         cg = np.array([[self.glb[e * lx ** 3 + c] for c in corner] for e in range(E)])
@@ -403,15 +447,65 @@ class Problem:
         return self
 
     def schwarz_apply(self, r, coarse_iters=10):
-        """z = M^{-1} r for an assembled, masked residual r: the local solves summed over
-        the shared points and averaged by multiplicity, plus the coarse correction P e0,
+        """z = M^{-1} r for an assembled, masked residual r: the local solves (on the
+        element's own points) summed over the shared points and averaged by multiplicity,
+        plus the coarse correction P e0,
         e0 from coarse_iters Jacobi-CG steps on A0 e0 = P^T r (from e0 = 0); masked."""
         lx, E = self.lx, self.nelv
-        rl = np.asarray(r, dtype=np.float64).reshape(E, lx ** 3)
-        zl = np.stack([np.linalg.solve(self._loc[e], rl[e]) for e in range(E)]).reshape(-1)
+        r = np.asarray(r, dtype=np.float64)
+        if self._overlap:
+            zl = np.zeros((E, lx ** 3))
+            for e, (Ainv, gather, own) in enumerate(self._ov):
+                rhs = np.where(gather >= 0, r[np.maximum(gather, 0)], 0.0)
+                zl[e] = (Ainv @ rhs)[own]
+            zl = zl.reshape(-1)
+        else:
+            rl = r.reshape(E, lx ** 3)
+            zl = np.stack([np.linalg.solve(self._loc[e], rl[e]) for e in range(E)]).reshape(-1)
         z = self.gs.op(zl) / self.mult
         out = z + self.coarse_correction(r, coarse_iters)
         out[self.dirichlet.astype(bool)] = 0.0
+        return out
+
+    def _extension_sources(self):
+        """For element e and face (d, side) (face index 2 d + side; the face's points
+        have local coordinate d equal to 0, or lx - 1 for side 1): None when no other
+        element holds every global id of the face, else a dict from each face point's
+        local index p to the index, in the whole local layout, of its extension point --
+        in that neighbour, the point adjacent (one GLL index away) to the copy of p whose
+        global id is not one of e's.  Brute force over global ids; any orientation."""
+        lx, N, E, lx3 = self.lx, self.lx - 1, self.nelv, self.lx ** 3
+        g = np.asarray(self.glb).reshape(E, lx3)
+        ids = [set(g[e].tolist()) for e in range(E)]
+        holders = {}
+        for e in range(E):
+            for v in ids[e]:
+                holders.setdefault(v, set()).add(e)
+        where = [{v: p for p, v in enumerate(g[e].tolist())} for e in range(E)]
+        out = []
+        for e in range(E):
+            faces = []
+            for d in range(3):
+                for side in (0, 1):
+                    pts = [p for p in range(lx3) if (p // lx ** d) % lx == (N if side else 0)]
+                    common = set.intersection(*(holders[g[e, p]] for p in pts)) - {e}
+                    if not common:
+                        faces.append(None)
+                        continue
+                    (e2,) = common
+                    m = {}
+                    for p in pts:
+                        q = where[e2][g[e, p]]
+                        cand = []
+                        for dd in range(3):
+                            c = (q // lx ** dd) % lx
+                            for s in (-1, 1):
+                                if 0 <= c + s <= N and g[e2, q + s * lx ** dd] not in ids[e]:
+                                    cand.append(q + s * lx ** dd)
+                        (q2,) = cand
+                        m[p] = e2 * lx3 + q2
+                    faces.append(m)
+            out.append(faces)
         return out
 
     def coarse_correction(self, r, coarse_iters=10):
