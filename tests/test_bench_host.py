@@ -62,18 +62,21 @@ def test_profile_summary_scales_counters_by_the_copy(monkeypatch, tmp_path):
                [["void sem::k_ax_helm<8, double, 1, false>(sem::AxArgs<double>, sem::DEo<8, double>)", 2, 400000,
                  200000, 60.0],
                 ["__amd_rocclr_copyBuffer", 1, 300000, 300000, 40.0]])
-    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value", "Grid_Size"]
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Grid_Size"]
+    # the reference is the first copy of the largest grid (dispatch 2); a later copy of
+    # the same grid (dispatch 9, partly served from cache) must not be taken
     _write_csv(tmp_path / "fetch" / "x_counter_collection.csv", hdr,
-               [["void sem::k_ax_helm<8, double, 1, false>(sem::AxArgs<double>, sem::DEo<8, double>)", "FETCH_SIZE",
-                 1000.0, 4096],
-                ["void sem::k_ax_helm<8, double, 1, false>(sem::AxArgs<double>, sem::DEo<8, double>)", "FETCH_SIZE",
-                 3000.0, 4096],
-                ["__amd_rocclr_copyBuffer", "FETCH_SIZE", 524288.0, 131072],
-                ["__amd_rocclr_copyBuffer", "FETCH_SIZE", 10.0, 64]])
+               [[5, "void sem::k_ax_helm<8, double, 1, false>(sem::AxArgs<double>, sem::DEo<8, double>)",
+                 "FETCH_SIZE", 1000.0, 4096],
+                [6, "void sem::k_ax_helm<8, double, 1, false>(sem::AxArgs<double>, sem::DEo<8, double>)",
+                 "FETCH_SIZE", 3000.0, 4096],
+                [9, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 100000.0, 131072],
+                [2, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 524288.0, 131072],
+                [1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 10.0, 64]])
     _write_csv(tmp_path / "write" / "x_counter_collection.csv", hdr,
-               [["void sem::k_ax_helm<8, double, 1, false>(sem::AxArgs<double>, sem::DEo<8, double>)", "WRITE_SIZE",
-                 500.0, 4096],
-                ["__amd_rocclr_copyBuffer", "WRITE_SIZE", 1048576.0, 131072]])
+               [[5, "void sem::k_ax_helm<8, double, 1, false>(sem::AxArgs<double>, sem::DEo<8, double>)",
+                 "WRITE_SIZE", 500.0, 4096],
+                [2, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1048576.0, 131072]])
     out = tmp_path / "s.md"
     bench.summarize_profile(str(tmp_path / "trace"), str(tmp_path / "fetch"), str(tmp_path / "write"), str(out),
                             "test", "workload", ["cmd"], ["bench.py"])
