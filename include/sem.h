@@ -276,7 +276,8 @@ typedef struct {
     int max_iter;     /* total Arnoldi steps (>= 1)                                    */
     int restart;      /* Krylov dimension m of one cycle, 1..200                       */
     int precond;      /* 0: point Jacobi (the exact assembled diagonal); 1: two-level
-                         additive Schwarz (sem_schwarz_apply)                          */
+                         additive Schwarz (sem_schwarz_apply, overlap 0); 2: the same
+                         with the one-point overlap (sem_schwarz_apply, overlap 1)     */
     int use_x0;       /* 1: x holds the initial guess on entry; 0: start from 0         */
     int coarse_iters; /* precond 1: CG steps of each coarse solve (0 -> 10)             */
 } sem_gmres_params;
@@ -303,9 +304,23 @@ sem_status sem_gmres_solve(double *x, const double *b, sem_coef coef, sem_mesh m
  * assembled and masked; z: device FP64, not overlapping r.  The first call for a
  * (coef, gs) pair builds the data (host eigen-decompositions, eight operator
  * applications); changing h1 or h2 rebuilds it.  Device memory ~ (3 lx^2 + 3 lx + 8) per
- * element plus one byte per point, plus the coarse system. */
+ * element plus one byte per point, plus the coarse system.
+ *
+ * overlap = 1: the minimal overlap of one point (Section 4 names an overlapping
+ * Schwarz method).  Every local problem also holds, beyond each face the element
+ * shares with a neighbour (found from the global ids: the other element holding the
+ * face's points, in any orientation), the layer of that neighbour's points one GLL
+ * index inside it, with the neighbour's residual as right-hand side; along that
+ * direction the extension node is joined to the face node by the first-spacing
+ * segment and held by a Dirichlet condition one second GLL spacing beyond it.  Faces
+ * without a neighbour keep the overlap-0 segment; the box's edge and corner points
+ * get zero right-hand side.  Each local solution is kept on the element's own points
+ * only (restricted additive Schwarz), then summed and averaged as above.  Extra
+ * device memory ~ (3 (lx+2)^2 + 3 (lx+2)) doubles and 24 int32 per element, built on
+ * the first overlap call; SEM_ERR_INVALID if a face is held by more than two elements
+ * or two elements share a face's corners but not its points.  overlap: 0 or 1. */
 sem_status sem_schwarz_apply(double *z, const double *r, sem_coef coef, sem_mesh msh, sem_space Xh,
-                             sem_gs gs, int coarse_iters, void *stream);
+                             sem_gs gs, int coarse_iters, int overlap, void *stream);
 
 /* ---------------------------------------------------------------- projection space
  * Initial guesses from previous solutions (the paper keeps a space of 20 previous

@@ -1,7 +1,7 @@
 """Build libsem.so (HIP for gfx950) in-tree.
 
-ax_kernels.hip is compiled once per supported lx (2..16) so the instantiations
-build in parallel; the objects are linked with the vector kernels, the host
+ax_kernels.hip and schwarz_kernels.hip are compiled once per supported lx (2..16)
+so the instantiations build in parallel; the objects are linked with the vector kernels, the host
 setup code and the C ABI into paper_2107_01243_amd/libsem.so.
 
 Usage: python paper_2107_01243_amd/build.py [--jobs N]   (run by path: importing the
@@ -46,6 +46,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         obj = os.path.join(BUILD, f"ax_lx{lx}.o")
         steps.append([HIPCC, *DEVICE_FLAGS, f"-DSEM_LX={lx}", "-c",
                       os.path.join(CSRC, "ax_kernels.hip"), "-o", obj])
+        steps.append([HIPCC, *DEVICE_FLAGS, f"-DSEM_LX={lx}", "-c",
+                      os.path.join(CSRC, "schwarz_kernels.hip"), "-o", os.path.join(BUILD, f"schwarz_lx{lx}.o")])
     for src in ("vec_kernels.hip", "sem_noalloc.hip", "sem_api.cpp", "sem_cg.cpp", "sem_proj.cpp",
                 "sem_gmres.cpp", "host_setup.cpp"):
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")

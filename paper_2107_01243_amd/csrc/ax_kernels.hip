@@ -26,6 +26,7 @@
 #include <string.h>
 
 #include "sem_kernels.h"
+#include "sem_pencil.h"
 
 #ifndef SEM_LX
 #error "compile with -DSEM_LX=<lx>"
@@ -84,26 +85,6 @@ template <int LX, typename T>
 struct Lds {
     T buf[2][Shape<LX, T>::EPB][Shape<LX, T>::ESZ];
 };
-
-// Synchronise the lanes that share one element's LDS buffers.  When whole elements
-// fit inside one wave64 (lx*lx divides 64, e.g. lx = 8: one element per wave) no
-// other wave touches those buffers, and LDS operations of one wave complete in
-// order, so a wave-level barrier (a compiler fence, no s_barrier) suffices.
-template <int LX>
-__device__ __forceinline__ void esync()
-{
-    if constexpr (64 % (LX * LX) == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-        __syncthreads();
-    }
-}
-
-// LDS index of point (i, j, k) inside one element buffer.
-template <int LX>
-__device__ __forceinline__ int lidx(int i, int j, int k) { return i + (LX + 1) * (j + LX * k); }
 
 // out = D in   (derivative along the pencil), even-odd form
 template <int LX, typename T>
@@ -1076,180 +1057,6 @@ __global__ SEM_BOUNDS2((Shape<LX, T>::NT), (Shape<LX, T>::MINW)) void k_ax_adjoi
     else adj_lean_body<LX, T>(DArg<LX, T>{D}, A);
 }
 
-// ------------------------------------------------------------------ Schwarz local solves
-// y = M x along one pencil, M row-major (a copy of S or of its transpose in LDS),
-// each y[m] summed over ascending l.
-template <int LX>
-__device__ __forceinline__ void fdm_mul(const double *M, const double (&x)[LX], double (&y)[LX])
-{
-#pragma unroll
-    for (int m = 0; m < LX; ++m) {
-        double s = M[m * LX] * x[0];
-#pragma unroll
-        for (int l = 1; l < LX; ++l) s = fma(M[m * LX + l], x[l], s);
-        y[m] = s;
-    }
-}
-
-// One element per workgroup of lx^2 lanes.  Lane t = a + lx b keeps its t-pencil
-// (i = a, j = b) in registers, so the two t-direction transforms are register-only;
-// the r- and s-direction transforms go through the element in LDS (row stride lx+1,
-// as in ax_helm).  The element's S and lambda (different in every element) are
-// staged in LDS with coalesced loads and read back as broadcasts; S is staged twice,
-// transposed for the forward transforms and as is for the inverse ones, so that the
-// two phases read distinct arrays and no matrix stays live in registers between them.
-// Forward t, forward r, then along s: forward, divide by h1 (lr_a + ls_j + lt_b) + h2,
-// inverse; then inverse r and inverse t.
-template <int LX>
-__global__ __launch_bounds__(LX * LX) void k_fdm(FdmArgs A)
-{
-    constexpr int L2 = LX * LX, L3 = L2 * LX;
-    __shared__ double cube[L2 * (LX + 1)];
-    __shared__ double red[2 * L2 + 4 * LX];
-    __shared__ __align__(16) double Sf[3 * L2];  // S^T per direction (forward)
-    __shared__ __align__(16) double Si[3 * L2];  // S per direction (inverse)
-    __shared__ double lam[3 * LX];
-    const int64_t e = blockIdx.x;
-    const int t = threadIdx.x, a = t % LX, b = t / LX;
-    {
-        const double *Se = A.S + e * 3 * L2;
-        for (int q = t; q < 3 * L2; q += L2) {
-            const double v = Se[q];
-            const int d = q / L2, l = (q % L2) / LX, m = q % LX;
-            Si[q] = v;
-            Sf[d * L2 + m * LX + l] = v;
-        }
-        const double *le = A.lam + e * 3 * LX;
-        for (int q = t; q < 3 * LX; q += L2) lam[q] = le[q];
-    }
-    const double *__restrict__ lin = A.lin;
-    double x[LX], y[LX];
-    const double *r = A.r + e * L3;
-#pragma unroll
-    for (int k = 0; k < LX; ++k) x[k] = r[k * L2 + t];
-    constexpr int NQ = (8 + L2 - 1) / L2;
-    double pr[NQ];
-    if (A.part) {
-        // coarse restriction: owned values against the linear functions along t in
-        // registers, then along s and r through LDS, in a fixed order
-        const uint8_t *ow = A.owner + e * L3;
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int k = 0; k < LX; ++k) {
-            const double v = ow[k * L2 + t] ? x[k] : 0.0;
-            s0 = fma(lin[k], v, s0);
-            s1 = fma(lin[LX + k], v, s1);
-        }
-        red[t] = s0;
-        red[L2 + t] = s1;
-        esync<LX>();
-        for (int q = t; q < 4 * LX; q += L2) {
-            const int i = q % LX, cb = q / LX;  // cb = (j side) + 2 (k side)
-            const double *rk = red + (cb >> 1) * L2 + i;
-            const double *lj = lin + (cb & 1) * LX;
-            double s = 0.0;
-            for (int j = 0; j < LX; ++j) s = fma(lj[j], rk[LX * j], s);
-            red[2 * L2 + q] = s;
-        }
-        esync<LX>();
-#pragma unroll
-        for (int h = 0; h < NQ; ++h) {
-            const int q = t + h * L2;
-            if (q >= 8) break;
-            const double *li = lin + (q & 1) * LX;
-            const double *u = red + 2 * L2 + (q >> 1) * LX;
-            double s = 0.0;
-            for (int i = 0; i < LX; ++i) s = fma(li[i], u[i], s);
-            pr[h] = s;
-        }
-    }
-    esync<LX>();  // S and lambda staged
-    fdm_mul<LX>(Sf + 2 * L2, x, y);
-#pragma unroll
-    for (int k = 0; k < LX; ++k) cube[lidx<LX>(a, b, k)] = y[k];
-    esync<LX>();
-    // r-pencil (j = a, k = b)
-#pragma unroll
-    for (int i = 0; i < LX; ++i) x[i] = cube[lidx<LX>(i, a, b)];
-    fdm_mul<LX>(Sf, x, y);
-#pragma unroll
-    for (int i = 0; i < LX; ++i) cube[lidx<LX>(i, a, b)] = y[i];
-    esync<LX>();
-    // s-pencil (i = a, k = b)
-#pragma unroll
-    for (int j = 0; j < LX; ++j) x[j] = cube[lidx<LX>(a, j, b)];
-    fdm_mul<LX>(Sf + L2, x, y);
-    {
-        const double lra = lam[a], ltb = lam[2 * LX + b];
-#pragma unroll
-        for (int j = 0; j < LX; ++j) y[j] /= A.h1 * (lra + lam[LX + j] + ltb) + A.h2;
-    }
-    fdm_mul<LX>(Si + L2, y, x);
-#pragma unroll
-    for (int j = 0; j < LX; ++j) cube[lidx<LX>(a, j, b)] = x[j];
-    esync<LX>();
-#pragma unroll
-    for (int i = 0; i < LX; ++i) y[i] = cube[lidx<LX>(i, a, b)];
-    fdm_mul<LX>(Si, y, x);
-#pragma unroll
-    for (int i = 0; i < LX; ++i) cube[lidx<LX>(i, a, b)] = x[i];
-    esync<LX>();
-#pragma unroll
-    for (int k = 0; k < LX; ++k) y[k] = cube[lidx<LX>(a, b, k)];
-    fdm_mul<LX>(Si + 2 * L2, y, x);
-    double *z = A.z + e * L3;
-#pragma unroll
-    for (int k = 0; k < LX; ++k) z[k * L2 + t] = x[k];
-    if (A.part) {
-#pragma unroll
-        for (int h = 0; h < NQ; ++h) {
-            const int q = t + h * L2;
-            if (q >= 8) break;
-            A.part[e * 8 + q] = pr[h];
-        }
-    }
-}
-
-// Coarse prolongation: the element's eight coarse values interpolated trilinearly
-// (along r, then s on the two t faces, then t per point), added to the
-// multiplicity-averaged local solution.  Lanes as in the t-pencil layout; whole
-// elements per workgroup.
-template <int LX>
-struct ProlongShape {
-    static constexpr int L2 = LX * LX;
-    static constexpr int EPB = 256 / L2 > 0 ? 256 / L2 : 1;
-    static constexpr int NT = EPB * L2;
-};
-
-template <int LX>
-__global__ __launch_bounds__(ProlongShape<LX>::NT) void k_prolong(ProlongArgs A)
-{
-    constexpr int L2 = LX * LX, L3 = L2 * LX, EPB = ProlongShape<LX>::EPB;
-    const int el = threadIdx.x / L2, t = threadIdx.x - el * L2;
-    const int64_t e = (int64_t)blockIdx.x * EPB + el;
-    if (e >= A.nelv) return;
-    const int a = t % LX, b = t / LX;
-    const double *__restrict__ lin = A.lin;
-    double c[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) c[q] = A.e0[A.cvert[e * 8 + q]];
-    const double ra0 = lin[a], ra1 = lin[LX + a], sb0 = lin[b], sb1 = lin[LX + b];
-    double f[2];
-#pragma unroll
-    for (int kc = 0; kc < 2; ++kc) {
-        const double y0 = fma(ra1, c[4 * kc + 1], ra0 * c[4 * kc]);
-        const double y1 = fma(ra1, c[4 * kc + 3], ra0 * c[4 * kc + 2]);
-        f[kc] = fma(sb1, y1, sb0 * y0);
-    }
-    double *z = A.z + e * L3;
-    const uint8_t *mu = A.mult + e * L3;
-#pragma unroll
-    for (int k = 0; k < LX; ++k) {
-        const double v = fma(lin[LX + k], f[1], lin[k] * f[0]);
-        z[k * L2 + t] = z[k * L2 + t] / (double)mu[k * L2 + t] + v;
-    }
-}
-
 // ------------------------------------------------------------------ h1-adjoint
 // g = (D v)^T G (D u) per point.
 template <int LX, typename T>
@@ -1546,23 +1353,6 @@ hipError_t SEM_PASTE(sem_launch_cg1_f64_lx, SEM_LX)(const sem::CgMatvecArgs<doub
                                                      const double *D, int nfields, hipStream_t st)
 {
     return launch_cg<double, true>(*A, D, nfields, st);
-}
-hipError_t SEM_PASTE(sem_launch_fdm_lx, SEM_LX)(const sem::FdmArgs *A, hipStream_t st)
-{
-    if (A->nelv == 0) return hipSuccess;
-    if (A->nelv > 0x7fffffff) return hipErrorInvalidValue;
-    if (A->part && (!A->owner || !A->lin)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sem::k_fdm<SEM_LX>), dim3((unsigned)A->nelv), dim3(SEM_LX * SEM_LX), 0, st, *A);
-    return hipGetLastError();
-}
-hipError_t SEM_PASTE(sem_launch_prolong_lx, SEM_LX)(const sem::ProlongArgs *A, hipStream_t st)
-{
-    using Sh = sem::ProlongShape<SEM_LX>;
-    if (A->nelv == 0) return hipSuccess;
-    const int64_t g = (A->nelv + Sh::EPB - 1) / Sh::EPB;
-    if (g > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sem::k_prolong<SEM_LX>), dim3((unsigned)g), dim3(Sh::NT), 0, st, *A);
-    return hipGetLastError();
 }
 hipError_t SEM_PASTE(sem_launch_adj_f64_lx, SEM_LX)(const sem::AdjArgs<double> *A, const double *D,
                                                      hipStream_t st)

@@ -279,4 +279,105 @@ void sym_eig(int n, double *a, double *V, double *lam)
     for (int i = 0; i < n; ++i) lam[i] = a[i * n + i];
 }
 
+namespace {
+
+// local index of the point with coordinate d equal to c and the two other
+// coordinates (ascending direction order) equal to fa, fb
+inline int64_t face_point(int lx, int d, int c, int fa, int fb)
+{
+    const int64_t l1 = lx, l2 = (int64_t)lx * lx;
+    if (d == 0) return c + l1 * fa + l2 * fb;
+    if (d == 1) return fa + l1 * c + l2 * fb;
+    return fa + l1 * fb + l2 * c;
+}
+
+}  // namespace
+
+bool face_neighbours(int64_t nelv, int lx, const int64_t *glb, std::vector<int32_t> &out, std::string &msg)
+{
+    const int N = lx - 1;
+    const int64_t lx3 = (int64_t)lx * lx * lx;
+    out.assign((size_t)nelv * 24, 0);
+    for (int64_t q = 0; q < nelv * 6; ++q) out[(size_t)q * 4] = -1;
+    if (nelv > 0x7fffffff / 6) {
+        msg = "face_neighbours: too many elements";
+        return false;
+    }
+    // faces keyed by their sorted corner ids
+    struct Rec {
+        int64_t key[4];
+        int32_t ef;  // e * 6 + f
+    };
+    std::vector<Rec> rec((size_t)nelv * 6);
+    parallel_for(nelv, [&](int64_t e0, int64_t e1) {
+        for (int64_t e = e0; e < e1; ++e)
+            for (int f = 0; f < 6; ++f) {
+                Rec &r = rec[(size_t)e * 6 + f];
+                const int d = f / 2, c = (f & 1) ? N : 0;
+                int q = 0;
+                for (int fb = 0; fb <= N; fb += N)
+                    for (int fa = 0; fa <= N; fa += N) r.key[q++] = glb[e * lx3 + face_point(lx, d, c, fa, fb)];
+                std::sort(r.key, r.key + 4);
+                r.ef = (int32_t)(e * 6 + f);
+            }
+    }, 4096);
+    std::sort(rec.begin(), rec.end(), [](const Rec &x, const Rec &y) {
+        return std::lexicographical_compare(x.key, x.key + 4, y.key, y.key + 4) ||
+               (std::equal(x.key, x.key + 4, y.key) && x.ef < y.ef);
+    });
+    // for face A = (e, f) and its partner B = (e2, f2): B's inward point under A's
+    // face point (fa, fb) is base + fa sa + fb sb, checked on every face point
+    auto link = [&](int32_t A, int32_t B) -> bool {
+        const int64_t e = A / 6, e2 = B / 6;
+        const int f = A % 6, f2 = B % 6, d = f / 2, d2 = f2 / 2;
+        const int c = (f & 1) ? N : 0, c2 = (f2 & 1) ? N : 0;
+        // B's face coordinates of each of A's corners
+        int img[3][2];
+        const int ca[3][2] = {{0, 0}, {N, 0}, {0, N}};
+        for (int m = 0; m < 3; ++m) {
+            const int64_t g = glb[e * lx3 + face_point(lx, d, c, ca[m][0], ca[m][1])];
+            bool hit = false;
+            for (int gb = 0; gb <= N && !hit; gb += N)
+                for (int ga = 0; ga <= N && !hit; ga += N)
+                    if (glb[e2 * lx3 + face_point(lx, d2, c2, ga, gb)] == g) {
+                        img[m][0] = ga;
+                        img[m][1] = gb;
+                        hit = true;
+                    }
+            if (!hit) return false;
+        }
+        const int64_t p0 = face_point(lx, d2, c2, img[0][0], img[0][1]);
+        const int64_t pa = face_point(lx, d2, c2, img[1][0], img[1][1]);
+        const int64_t pb = face_point(lx, d2, c2, img[2][0], img[2][1]);
+        const int64_t sa = (pa - p0) / N, sb = (pb - p0) / N;
+        if (sa * N != pa - p0 || sb * N != pb - p0) return false;
+        for (int fb = 0; fb <= N; ++fb)
+            for (int fa = 0; fa <= N; ++fa)
+                if (glb[e * lx3 + face_point(lx, d, c, fa, fb)] != glb[e2 * lx3 + p0 + fa * sa + fb * sb])
+                    return false;
+        int64_t stride = 1;
+        for (int k = 0; k < d2; ++k) stride *= lx;
+        int32_t *o = &out[(size_t)A * 4];
+        o[0] = (int32_t)e2;
+        o[1] = (int32_t)(p0 + ((f2 & 1) ? -stride : stride));
+        o[2] = (int32_t)sa;
+        o[3] = (int32_t)sb;
+        return true;
+    };
+    for (size_t q = 0; q < rec.size();) {
+        size_t q2 = q + 1;
+        while (q2 < rec.size() && std::equal(rec[q].key, rec[q].key + 4, rec[q2].key)) ++q2;
+        if (q2 - q > 2) {
+            msg = "face_neighbours: a face is shared by more than two elements";
+            return false;
+        }
+        if (q2 - q == 2 && (!link(rec[q].ef, rec[q + 1].ef) || !link(rec[q + 1].ef, rec[q].ef))) {
+            msg = "face_neighbours: two elements share a face's corners but not its points as a grid";
+            return false;
+        }
+        q = q2;
+    }
+    return true;
+}
+
 }  // namespace semh

@@ -8,10 +8,38 @@ using namespace semi;
 extern "C" {
 
 // ------------------------------------------------------------------ two-level Schwarz
+// Per element and direction d, sum over the element of G_dd / B (formed on the
+// device): the element length is L_d = 2 / sqrt(that sum / lx^3).
+static sem_status elem_gb(sem_coef c, hipStream_t st, std::vector<double> &gb)
+{
+    const int lx3 = c->lx * c->lx * c->lx;
+    gb.assign((size_t)3 * c->nelv, 0.0);
+    double *d_gb = nullptr;
+    SEM_TRY(dalloc(&d_gb, gb.size()));
+    const hipError_t e1 = sem_launch_elem_gb(c->G, c->B, d_gb, c->nelv, lx3, st);
+    const hipError_t e2 =
+        e1 == hipSuccess ? hipMemcpyAsync(gb.data(), d_gb, sizeof(double) * gb.size(), hipMemcpyDeviceToHost, st) : e1;
+    const hipError_t e3 = e2 == hipSuccess ? hipStreamSynchronize(st) : e2;
+    dfree(d_gb);
+    HIP_TRY(e3);
+    return SEM_OK;
+}
+
+// 1-D GLL stiffness on [-1, 1]: Kref[m][q] = sum_i w_i D_im D_iq
+static std::vector<double> ref_stiffness(sem_space Xh)
+{
+    const int lx = Xh->lx;
+    std::vector<double> Kref((size_t)lx * lx, 0.0);
+    for (int m = 0; m < lx; ++m)
+        for (int q = 0; q < lx; ++q)
+            for (int i = 0; i < lx; ++i) Kref[m * lx + q] += Xh->w[i] * Xh->D[i * lx + m] * Xh->D[i * lx + q];
+    return Kref;
+}
+
 // Setup (host + a few launches): element lengths from the geometric factors, the
 // 1-D extended operators and their eigen-decompositions, the coarse vertices and
 // the Galerkin coarse matrix from eight probe applications of A_L.
-static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
+static sem_status schwarz_setup_base(sem_coef c, sem_gs g, hipStream_t st)
 {
     SchwarzData &Z = c->sz;
     if (Z.valid && Z.gs == (const void *)g) return SEM_OK;
@@ -20,24 +48,9 @@ static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
     const int lx = c->lx, N = lx - 1, lx3 = lx * lx * lx;
     const int64_t E = c->nelv, n = c->n;
     const sem_space Xh = c->Xh;
-    // element lengths: L_d = 2 / sqrt(mean over the element of G_dd / B), the sums
-    // formed on the device
-    std::vector<double> gb((size_t)3 * E);
-    {
-        double *d_gb = nullptr;
-        SEM_TRY(dalloc(&d_gb, gb.size()));
-        const hipError_t e1 = sem_launch_elem_gb(c->G, c->B, d_gb, E, lx3, st);
-        const hipError_t e2 = e1 == hipSuccess
-                                  ? hipMemcpyAsync(gb.data(), d_gb, sizeof(double) * gb.size(), hipMemcpyDeviceToHost, st)
-                                  : e1;
-        const hipError_t e3 = e2 == hipSuccess ? hipStreamSynchronize(st) : e2;
-        dfree(d_gb);
-        HIP_TRY(e3);
-    }
-    std::vector<double> Kref((size_t)lx * lx, 0.0);
-    for (int m = 0; m < lx; ++m)
-        for (int q = 0; q < lx; ++q)
-            for (int i = 0; i < lx; ++i) Kref[m * lx + q] += Xh->w[i] * Xh->D[i * lx + m] * Xh->D[i * lx + q];
+    std::vector<double> gb;
+    SEM_TRY(elem_gb(c, st, gb));
+    const std::vector<double> Kref = ref_stiffness(Xh);
     const double dref = Xh->xi[1] - Xh->xi[0];
     std::vector<double> S((size_t)E * 3 * lx * lx), lam((size_t)E * 3 * lx);
     semh::parallel_for(E, [&](int64_t e0, int64_t e1) {
@@ -224,13 +237,95 @@ static sem_status schwarz_setup(sem_coef c, sem_gs g, hipStream_t st)
     return SEM_OK;
 }
 
-// z = M^{-1} r: local solves summed over shared points and averaged, plus P e0 from
-// coarse_iters Jacobi-CG steps on A0 e0 = P^T r; masked.  r assembled and masked.
-static sem_status schwarz_apply(sem_coef c, sem_gs g, double *z, const double *r, int coarse_iters, hipStream_t st)
+// The one-point overlap: the face-neighbour table, and per element and direction the
+// 1-D operator on lx + 2 nodes (extension node, the element's GLL nodes, extension
+// node).  Beyond a face with a neighbour the extension node is joined to the face node
+// by a linear segment of the first GLL spacing and held by a Dirichlet condition one
+// second GLL spacing further out; beyond a face without one, the face node keeps the
+// first-spacing segment (Dirichlet at its end) and the extension node is decoupled
+// (K = 1/h, M = h/2: its zero right-hand side gives zero there, so the own points see
+// the element-only problem in that direction).
+static sem_status schwarz_setup_overlap(sem_coef c, hipStream_t st)
+{
+    SchwarzData &Z = c->sz;
+    if (Z.ov_valid) return SEM_OK;
+    const int lx = c->lx, N = lx - 1, X = lx + 2, lx3 = lx * lx * lx;
+    const int64_t E = c->nelv;
+    const sem_space Xh = c->Xh;
+    std::vector<int32_t> face;
+    std::string msg;
+    if (!semh::face_neighbours(E, lx, c->msh->glb.data(), face, msg)) return fail(SEM_ERR_INVALID, "%s", msg.c_str());
+    std::vector<double> gb;
+    SEM_TRY(elem_gb(c, st, gb));
+    const std::vector<double> Kref = ref_stiffness(Xh);
+    const int i2 = N >= 2 ? 2 : N;
+    const double dref = Xh->xi[1] - Xh->xi[0], dref2 = Xh->xi[i2] - Xh->xi[i2 - 1];
+    std::vector<double> S((size_t)E * 3 * X * X), lam((size_t)E * 3 * X);
+    semh::parallel_for(E, [&](int64_t e0, int64_t e1) {
+        std::vector<double> K((size_t)X * X), a((size_t)X * X), V((size_t)X * X), l(X), M(X);
+        for (int64_t e = e0; e < e1; ++e) {
+            for (int d = 0; d < 3; ++d) {
+                const double L = 2.0 / std::sqrt(gb[(size_t)e * 3 + d] / lx3), J = L / 2.0;
+                const double h = J * dref, h2 = J * dref2;
+                std::fill(K.begin(), K.end(), 0.0);
+                std::fill(M.begin(), M.end(), 0.0);
+                for (int i = 0; i < lx; ++i) {
+                    M[i + 1] = Xh->w[i] * J;
+                    for (int q = 0; q < lx; ++q) K[(i + 1) * X + q + 1] = Kref[i * lx + q] / J;
+                }
+                for (int side = 0; side < 2; ++side) {
+                    const bool has = face[((size_t)e * 6 + 2 * d + side) * 4] >= 0;
+                    const int f = side ? lx : 1, xn = side ? X - 1 : 0;
+                    K[f * X + f] += 1.0 / h;
+                    M[f] += h / 2.0;
+                    if (has) {
+                        K[xn * X + xn] += 1.0 / h + 1.0 / h2;
+                        K[xn * X + f] -= 1.0 / h;
+                        K[f * X + xn] -= 1.0 / h;
+                        M[xn] += h / 2.0 + h2 / 2.0;
+                    } else {
+                        K[xn * X + xn] = 1.0 / h;
+                        M[xn] = h / 2.0;
+                    }
+                }
+                for (int i = 0; i < X; ++i)
+                    for (int q = 0; q < X; ++q) a[i * X + q] = K[i * X + q] / std::sqrt(M[i] * M[q]);
+                semh::sym_eig(X, a.data(), V.data(), l.data());
+                double *Sd = &S[((size_t)e * 3 + d) * X * X];
+                for (int i = 0; i < X; ++i)
+                    for (int m = 0; m < X; ++m) Sd[i * X + m] = V[i * X + m] / std::sqrt(M[i]);
+                for (int m = 0; m < X; ++m) lam[((size_t)e * 3 + d) * X + m] = l[m];
+            }
+        }
+    }, 64);
+    SEM_TRY(dalloc(&Z.S_ov, S.size()));
+    SEM_TRY(dalloc(&Z.lam_ov, lam.size()));
+    SEM_TRY(dalloc(&Z.face, face.size()));
+    HIP_TRY(hipMemcpy(Z.S_ov, S.data(), S.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(Z.lam_ov, lam.data(), lam.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(Z.face, face.data(), face.size() * 4, hipMemcpyHostToDevice));
+    Z.ov_valid = true;
+    return SEM_OK;
+}
+
+static sem_status schwarz_setup(sem_coef c, sem_gs g, bool overlap, hipStream_t st)
+{
+    SEM_TRY(schwarz_setup_base(c, g, st));
+    if (overlap) SEM_TRY(schwarz_setup_overlap(c, st));
+    return SEM_OK;
+}
+
+// z = M^{-1} r: local solves (on the element's box, or with overlap on the box
+// extended by one point, keeping the own points) summed over shared points and
+// averaged, plus P e0 from coarse_iters Jacobi-CG steps on A0 e0 = P^T r; masked.
+// r assembled and masked.
+static sem_status schwarz_apply(sem_coef c, sem_gs g, double *z, const double *r, int coarse_iters, bool overlap,
+                                hipStream_t st)
 {
     SchwarzData &Z = c->sz;
     const int lx = c->lx;
-    const FdmArgs F{z, r, Z.S, Z.lam, g->d_owner, Z.lin, Z.part, c->h1s, c->h2s, c->nelv};
+    const FdmArgs F{z,      r,      overlap ? Z.S_ov : Z.S, overlap ? Z.lam_ov : Z.lam, g->d_owner,
+                    Z.lin,  Z.part, overlap ? Z.face : nullptr, c->h1s, c->h2s, c->nelv};
     HIP_TRY(fns(lx).fdm(&F, st));
     SEM_TRY(launch_gs<double>(z, 1, g, nullptr, nullptr, st));
     const int64_t nv = Z.nv;
@@ -245,11 +340,12 @@ static sem_status schwarz_apply(sem_coef c, sem_gs g, double *z, const double *r
 }
 
 sem_status sem_schwarz_apply(double *z, const double *r, sem_coef coef, sem_mesh msh, sem_space Xh, sem_gs gs,
-                             int coarse_iters, void *stream)
+                             int coarse_iters, int ov, void *stream)
 {
     SEM_TRY(check_coef(coef, msh, Xh));
     if (!gs || gs->msh != msh) return fail(SEM_ERR_INVALID, "gs is NULL or built for another mesh");
     if (coarse_iters < 0 || coarse_iters > 10000) return fail(SEM_ERR_INVALID, "coarse_iters must be in 0..10000");
+    if (ov != 0 && ov != 1) return fail(SEM_ERR_INVALID, "overlap must be 0 or 1");
     const size_t bytes = (size_t)coef->n * 8;
     if (bytes == 0) return SEM_OK;
     if (!z || !r) return fail(SEM_ERR_INVALID, "z or r is NULL");
@@ -257,8 +353,8 @@ sem_status sem_schwarz_apply(double *z, const double *r, sem_coef coef, sem_mesh
     hipStream_t st = S(stream);
     SEM_TRY(gs_upload(gs));
     SEM_TRY(mesh_upload(msh));
-    SEM_TRY(schwarz_setup(coef, gs, st));
-    return schwarz_apply(coef, gs, z, r, coarse_iters, st);
+    SEM_TRY(schwarz_setup(coef, gs, ov != 0, st));
+    return schwarz_apply(coef, gs, z, r, coarse_iters, ov != 0, st);
 }
 
 // ------------------------------------------------------------------ flexible GMRES
@@ -270,11 +366,12 @@ static sem_status gmres_apply(sem_coef c, sem_gs g, double *w, const double *z, 
     return SEM_OK;
 }
 
-// z = M^{-1} v (0: point Jacobi; 1: two-level Schwarz)
+// z = M^{-1} v (0: point Jacobi; 1: two-level Schwarz; 2: the same with one-point overlap)
 static sem_status gmres_precond(sem_coef c, sem_gs g, const sem_gmres_params *P, double *z, const double *v,
                                 hipStream_t st)
 {
-    if (P->precond == 1) return schwarz_apply(c, g, z, v, P->coarse_iters > 0 ? P->coarse_iters : 10, st);
+    if (P->precond == 1 || P->precond == 2)
+        return schwarz_apply(c, g, z, v, P->coarse_iters > 0 ? P->coarse_iters : 10, P->precond == 2, st);
     HIP_TRY(sem_launch_hadamard(z, c->dinv, v, c->n, st));
     return SEM_OK;
 }
@@ -539,7 +636,7 @@ sem_status sem_gmres_solve(double *x, const double *b, sem_coef coef, sem_mesh m
     if (!(P.rtol > 0.0) || !std::isfinite(P.rtol)) return fail(SEM_ERR_INVALID, "rtol must be > 0");
     if (P.max_iter < 1) return fail(SEM_ERR_INVALID, "max_iter must be >= 1");
     if (P.restart < 1 || P.restart > 200) return fail(SEM_ERR_INVALID, "restart must be in 1..200");
-    if (P.precond != 0 && P.precond != 1) return fail(SEM_ERR_INVALID, "precond must be 0 or 1");
+    if (P.precond < 0 || P.precond > 2) return fail(SEM_ERR_INVALID, "precond must be 0, 1 or 2");
     if (P.coarse_iters < 0 || P.coarse_iters > 10000) return fail(SEM_ERR_INVALID, "coarse_iters must be in 0..10000");
     const size_t bytes = (size_t)coef->n * 8;
     if (bytes == 0) return SEM_OK;
@@ -550,7 +647,7 @@ sem_status sem_gmres_solve(double *x, const double *b, sem_coef coef, sem_mesh m
     SEM_TRY(mesh_upload(msh));
     SEM_TRY(ensure_dinv(coef, gs, st));
     SEM_TRY(ensure_work(coef, 1, false));
-    if (P.precond == 1) SEM_TRY(schwarz_setup(coef, gs, st));
+    if (P.precond != 0) SEM_TRY(schwarz_setup(coef, gs, P.precond == 2, st));
     sem_gmres_params Q = P;  // cycles and convergence work on SEM_RTOL_MARGIN * rtol
     Q.rtol *= SEM_RTOL_MARGIN;
     return gmres_run(x, b, coef, gs, &Q, info, st);

@@ -38,6 +38,18 @@ bool build_gs_maps(int64_t n, const int64_t *glb, const uint8_t *dir, GsMaps &m,
 void element_order(const GsMaps &m, std::vector<int32_t> &pairs, std::vector<int64_t> &blk_ptr,
                    std::vector<int32_t> &blk_idx);
 
+// Face neighbours of a conforming hexahedral mesh, from its global ids.  Face
+// f = 2 d + side of an element holds the points whose local coordinate d is 0 (side 0)
+// or lx - 1 (side 1); its face coordinates (fa, fb) are the two other local
+// coordinates in ascending direction order.  out[(e * 6 + f) * 4 + 0..3] =
+// {e2, base, sa, sb}: e2 the other element holding the face (every point of it, at
+// matching grid positions), and, for face point (fa, fb), base + fa sa + fb sb the
+// local index in e2 of the point one GLL index inside e2 from that point's copy;
+// e2 = -1 (and zeros) where no other element holds the face.  Returns false (msg
+// set) when a face is held by more than two elements or two elements share a face's
+// corners but not its points.
+bool face_neighbours(int64_t nelv, int lx, const int64_t *glb, std::vector<int32_t> &out, std::string &msg);
+
 // Symmetric eigen-decomposition a = V diag(lam) V^T of the n x n row-major matrix a
 // (destroyed) by cyclic Jacobi rotations; V row-major [row][mode].
 void sym_eig(int n, double *a, double *V, double *lam);

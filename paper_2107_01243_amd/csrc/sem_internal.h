@@ -279,11 +279,18 @@ struct SchwarzData {
     double *cv = nullptr;                 // [6][nv]: x, r, z, p0, p1, q
     double *cpart = nullptr;              // [3][ceil(nv / 256)]
     uint8_t *mult = nullptr;              // [n]
+    // one-point overlap (built on first use): local operators on the element box
+    // extended by one point beyond each face, and the face-neighbour table
+    bool ov_valid = false;
+    double *S_ov = nullptr, *lam_ov = nullptr;  // [nelv][3][lx+2][lx+2], [nelv][3][lx+2]
+    int32_t *face = nullptr;                    // [nelv][6][4]
     void release()
     {
         dfree(S); dfree(lam); dfree(phi); dfree(lin); dfree(cvert); dfree(v_ptr); dfree(v_idx); dfree(v_dir);
         dfree(ell_ci); dfree(ell_val); dfree(dinv0); dfree(part); dfree(cv); dfree(cpart);
         dfree(mult);
+        dfree(S_ov); dfree(lam_ov); dfree(face);
+        ov_valid = false;
         width = 0;
         valid = false;
         gs = nullptr;

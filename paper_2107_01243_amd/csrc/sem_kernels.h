@@ -120,17 +120,24 @@ struct DiagArgs {
 // Local solves of the two-level Schwarz preconditioner (fast diagonalisation):
 // z_e = (S_t x S_s x S_r) diag(1 / (h1 (lr_i + ls_j + lt_k) + h2)) (S_t x S_s x S_r)^T r_e,
 // with per element and direction the eigenvectors S (row-major [point][mode]) and
-// eigenvalues of the 1-D generalised problem K S = M S Lambda.  When part is set,
-// the same pass also forms the coarse restriction of r: per element the eight sums
-// over its owned points of r times the trilinear corner functions.
+// eigenvalues of the 1-D generalised problem K S = M S Lambda, on the element's own
+// box (X = lx points per direction) or, when face is set, on the box extended by one
+// point beyond each face (X = lx + 2; the extension layers' right-hand side is the
+// face neighbours' residual, see face; only the own points of z are written).  When
+// part is set, the same pass also forms the coarse restriction of r: per element the
+// eight sums over its owned points of r times the trilinear corner functions.
 struct FdmArgs {
     double *z;             // [nelv][lx^3]
     const double *r;       // [nelv][lx^3]
-    const double *S;       // [nelv][3][lx][lx]
-    const double *lam;     // [nelv][3][lx]
+    const double *S;       // [nelv][3][X][X]
+    const double *lam;     // [nelv][3][X]
     const uint8_t *owner;  // [nelv][lx^3] one copy per global id (restriction weights)
     const double *lin;     // [2][lx]: (1 - xi_i) / 2, (1 + xi_i) / 2 at the GLL points
     double *part;          // [nelv][8] restriction sums (corner c = a + 2 b + 4 c'), or nullptr
+    // [nelv][6][4] or nullptr: per face f = 2 d + side {e2, base, sa, sb}: the point of
+    // neighbour e2 under face point (fa, fb) (fa, fb the two other local coordinates,
+    // ascending direction order) is base + fa sa + fb sb in e2; e2 = -1: no neighbour
+    const int32_t *face;
     double h1, h2;
     int64_t nelv;
 };

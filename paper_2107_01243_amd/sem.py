@@ -79,7 +79,7 @@ _SIGS = {
     "sem_stream_triad": ([_vp, _vp, _vp, C.c_double, C.c_int64, _vp], C.c_int),
     "sem_gmres_solve": ([_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(GmresParams), C.POINTER(PcgInfo), _vp],
                         C.c_int),
-    "sem_schwarz_apply": ([_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _vp], C.c_int),
+    "sem_schwarz_apply": ([_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, _vp], C.c_int),
     "sem_proj_create": ([_vp, _vp, _vp, _vp, C.c_int, C.POINTER(_vp)], C.c_int),
     "sem_proj_size": ([_vp, _vp, _vp, _vp], C.c_int),
     "sem_proj_reset": ([_vp], C.c_int),
@@ -385,7 +385,7 @@ def pcg_solve_noalloc(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, nfields: i
 # SEM_NOALLOC_MAX_POINTS of sem.h
 NOALLOC_MAX_POINTS = 1 << 21
 
-GMRES_PRECOND = {"jacobi": 0, "schwarz": 1}
+GMRES_PRECOND = {"jacobi": 0, "schwarz": 1, "schwarz_overlap": 2}
 
 
 def gmres_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, rtol: float = 1e-10, max_iter: int = 100000,
@@ -410,12 +410,14 @@ def gmres_solve(x, b, coef: Coef, msh: Mesh, Xh: Space, gs: GS, rtol: float = 1e
     return d
 
 
-def schwarz_apply(z, r, coef: Coef, msh: Mesh, Xh: Space, gs: GS, coarse_iters: int = 10, stream=None):
-    """z = M0^{-1} r, the two-level additive Schwarz preconditioner (Section 4)."""
+def schwarz_apply(z, r, coef: Coef, msh: Mesh, Xh: Space, gs: GS, coarse_iters: int = 10, overlap: bool = False,
+                  stream=None):
+    """z = M0^{-1} r, the two-level additive Schwarz preconditioner (Section 4); with
+    overlap, the local problems extend one point into the face neighbours."""
     _dev(z, msh.n, "z")
     _dev(r, msh.n, "r")
     _check(_L.sem_schwarz_apply(_ptr(z), _ptr(r), coef._h, msh._h, Xh._h, gs._h, int(coarse_iters),
-                                _stream(stream)))
+                                int(bool(overlap)), _stream(stream)))
     return z
 
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <random>
 #include <string>
 #include <vector>
@@ -112,6 +113,72 @@ static void check_eig(int n, unsigned seed)
     CHECK(err <= 1e-12 * n * scale, "sym_eig n=%d err %.3e", n, err);
 }
 
+// Face neighbours on a box mesh whose elements are each re-indexed by a random one of
+// the 48 symmetries of the cube (axis permutation and flips): every face point's
+// extension point must be the grid point one step outward along the face's global
+// normal, present exactly when the element's face is inside the box.
+static void check_faces(int nx, int ny, int nz, int lx, unsigned seed)
+{
+    std::vector<double> xi(lx), w(lx), D(lx * lx);
+    semh::gll_space(lx, xi.data(), w.data(), D.data());
+    const int N = lx - 1;
+    const int64_t lx3 = (int64_t)lx * lx * lx, nelv = (int64_t)nx * ny * nz;
+    std::vector<int64_t> g0(nelv * lx3), glb(nelv * lx3);
+    semh::box_mesh(nx, ny, nz, lx, 0.0, xi.data(), g0.data(), nullptr, nullptr);
+    const int64_t Mx = (int64_t)nx * N + 1, My = (int64_t)ny * N + 1;
+    const int64_t gstride[3] = {1, Mx, Mx * My};
+    const int nel[3] = {nx, ny, nz};
+    std::mt19937_64 rng(seed);
+    std::vector<int> perm((size_t)nelv * 3), flip((size_t)nelv * 3);
+    for (int64_t e = 0; e < nelv; ++e) {
+        int s[3] = {0, 1, 2};
+        std::shuffle(s, s + 3, rng);
+        for (int m = 0; m < 3; ++m) {
+            perm[e * 3 + m] = s[m];
+            flip[e * 3 + m] = (int)(rng() & 1);
+        }
+        for (int64_t p = 0; p < lx3; ++p) {
+            const int c[3] = {(int)(p % lx), (int)((p / lx) % lx), (int)(p / (lx * lx))};
+            int cn[3];
+            for (int m = 0; m < 3; ++m) cn[m] = flip[e * 3 + m] ? N - c[perm[e * 3 + m]] : c[perm[e * 3 + m]];
+            glb[e * lx3 + cn[0] + lx * (cn[1] + lx * cn[2])] = g0[e * lx3 + p];
+        }
+    }
+    std::vector<int32_t> fn;
+    std::string msg;
+    const bool ok = semh::face_neighbours(nelv, lx, glb.data(), fn, msg);
+    CHECK(ok, "%s", msg.c_str());
+    if (!ok) return;
+    for (int64_t e = 0; e < nelv; ++e) {
+        const int64_t ec[3] = {e % nx, (e / nx) % ny, e / ((int64_t)nx * ny)};
+        for (int f = 0; f < 6; ++f) {
+            const int d = f / 2, side = f & 1;
+            const int ga = perm[e * 3 + d];                           // global axis of the normal
+            const int oldc = flip[e * 3 + d] ? N - side * N : side * N;  // old coordinate: 0 or N
+            const int dirn = oldc == 0 ? -1 : 1;
+            const bool inside = dirn < 0 ? ec[ga] > 0 : ec[ga] < nel[ga] - 1;
+            const int32_t *o = &fn[(size_t)(e * 6 + f) * 4];
+            CHECK((o[0] >= 0) == inside, "e %lld face %d neighbour %d", (long long)e, f, o[0]);
+            if (o[0] < 0 || !inside) continue;
+            for (int fb = 0; fb <= N; ++fb)
+                for (int fa = 0; fa <= N; ++fa) {
+                    int c[3];
+                    c[d] = side * N;
+                    c[d == 0 ? 1 : 0] = fa;
+                    c[d == 2 ? 1 : 2] = fb;
+                    const int64_t gp = glb[e * lx3 + c[0] + lx * (c[1] + lx * c[2])];
+                    const int64_t q = o[1] + (int64_t)fa * o[2] + (int64_t)fb * o[3];
+                    CHECK(q >= 0 && q < lx3, "e %lld face %d point (%d, %d): index %lld", (long long)e, f, fa, fb,
+                          (long long)q);
+                    if (q < 0 || q >= lx3) continue;
+                    CHECK(glb[(int64_t)o[0] * lx3 + q] == gp + dirn * gstride[ga],
+                          "e %lld face %d point (%d, %d): extension id %lld, want %lld", (long long)e, f, fa, fb,
+                          (long long)glb[(int64_t)o[0] * lx3 + q], (long long)(gp + dirn * gstride[ga]));
+                }
+        }
+    }
+}
+
 int main()
 {
     for (int lx = 2; lx <= 16; ++lx) check_space(lx);
@@ -124,6 +191,11 @@ int main()
     check_random_ids(5000, 37, 2);     // large groups (> 64 copies)
     check_random_ids(20000, 9000, 3);  // mostly pairs and singletons
     for (int n : {1, 2, 5, 14, 18}) check_eig(n, 10 + n);
+    check_faces(1, 1, 1, 3, 7);
+    check_faces(2, 1, 1, 2, 8);
+    check_faces(3, 2, 2, 4, 9);
+    check_faces(3, 3, 3, 5, 10);
+    check_faces(2, 3, 4, 8, 11);
     std::vector<int64_t> hits(100000, 0);
     semh::parallel_for((int64_t)hits.size(), [&](int64_t lo, int64_t hi) {
         for (int64_t i = lo; i < hi; ++i) hits[i] += 1;
