@@ -179,6 +179,32 @@ static void check_faces(int nx, int ny, int nz, int lx, unsigned seed)
     }
 }
 
+// Error paths of the face-neighbour builder: a face held by three elements (an element
+// repeated twice more), and two elements whose shared face corners match while the
+// points inside the face do not.
+static void check_faces_invalid()
+{
+    const int lx = 3;
+    const int64_t lx3 = 27;
+    std::vector<double> xi(lx), w(lx), D(lx * lx);
+    semh::gll_space(lx, xi.data(), w.data(), D.data());
+    std::vector<int64_t> one(lx3), glb(3 * lx3);
+    semh::box_mesh(1, 1, 1, lx, 0.0, xi.data(), one.data(), nullptr, nullptr);
+    for (int r = 0; r < 3; ++r)
+        for (int64_t p = 0; p < lx3; ++p) glb[r * lx3 + p] = one[p];
+    std::vector<int32_t> fn;
+    std::string msg;
+    CHECK(!semh::face_neighbours(3, lx, glb.data(), fn, msg), "three elements on one face accepted");
+    CHECK(msg.find("more than two") != std::string::npos, "message: %s", msg.c_str());
+    std::vector<int64_t> two(2 * lx3);
+    semh::box_mesh(2, 1, 1, lx, 0.0, xi.data(), two.data(), nullptr, nullptr);
+    // the shared face of element 1 is i = 0; give its centre point a fresh id
+    two[lx3 + 0 + lx * (1 + lx * 1)] = 1000000;
+    msg.clear();
+    CHECK(!semh::face_neighbours(2, lx, two.data(), fn, msg), "mismatched face interior accepted");
+    CHECK(msg.find("not its points") != std::string::npos, "message: %s", msg.c_str());
+}
+
 int main()
 {
     for (int lx = 2; lx <= 16; ++lx) check_space(lx);
@@ -196,6 +222,7 @@ int main()
     check_faces(3, 2, 2, 4, 9);
     check_faces(3, 3, 3, 5, 10);
     check_faces(2, 3, 4, 8, 11);
+    check_faces_invalid();
     std::vector<int64_t> hits(100000, 0);
     semh::parallel_for((int64_t)hits.size(), [&](int64_t lo, int64_t hi) {
         for (int64_t i = lo; i < hi; ++i) hits[i] += 1;
