@@ -50,7 +50,7 @@ typedef enum {
     SEM_ERR_HIP = -3,            /* a HIP runtime call failed (message has details)   */
     SEM_ERR_NOT_CONVERGED = -4,  /* solver hit max_iter; x and info are valid         */
     SEM_ERR_BREAKDOWN = -5,      /* non-positive or non-finite curvature in CG        */
-    SEM_ERR_UNSUPPORTED = -6     /* valid request this build does not implement      */
+    SEM_ERR_UNSUPPORTED = -6     /* valid request this library does not implement    */
 } sem_status;
 
 typedef enum { SEM_F64 = 0, SEM_F32 = 1 } sem_dtype;
