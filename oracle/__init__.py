@@ -468,7 +468,9 @@ class Problem:
         return out
 
     def _extension_sources(self):
-        """For element e and face (d, side) (face index 2 d + side; the face's points
+        """The neighbour points that extend each element's Schwarz subdomain by one
+        point (Section 4, overlapping subdomains of the additive Schwarz method).
+        For element e and face (d, side) (face index 2 d + side; the face's points
         have local coordinate d equal to 0, or lx - 1 for side 1): None when no other
         element holds every global id of the face, else a dict from each face point's
         local index p to the index, in the whole local layout, of its extension point --
