@@ -226,7 +226,7 @@ static sem_status schwarz_setup_base(sem_coef c, sem_gs g, hipStream_t st)
     SEM_TRY(dalloc(&Z.ell_val, evl.size()));
     SEM_TRY(dalloc(&Z.dinv0, (size_t)nv));
     SEM_TRY(dalloc(&Z.cv, (size_t)6 * nv));
-    SEM_TRY(dalloc(&Z.cpart, (size_t)3 * ((nv + 255) / 256)));
+    SEM_TRY(dalloc(&Z.cpart, (size_t)(2 + sem_coarse_split()) * ((nv + 255) / 256)));
     HIP_TRY(hipMemcpy(Z.ell_ci, eci.data(), eci.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(Z.ell_val, evl.data(), evl.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(Z.dinv0, dg.data(), dg.size() * 8, hipMemcpyHostToDevice));

@@ -89,6 +89,7 @@ hipError_t sem_launch_arn(const ArnArgs *, int, hipStream_t);
 hipError_t sem_launch_arn_finish(const double *, int64_t, int, int, double *, hipStream_t);
 hipError_t sem_launch_corner(const CornerArgs *, hipStream_t);
 hipError_t sem_launch_coarse_cg(const CoarseArgs *, int, hipStream_t);
+int sem_coarse_split();
 hipError_t sem_launch_elem_gb(const double *, const double *, double *, int64_t, int, hipStream_t);
 hipError_t sem_launch_probe(double *, const double *, int, int64_t, int, hipStream_t);
 hipError_t sem_launch_residual(double *, const double *, const double *, const double *, int64_t, int,
@@ -277,7 +278,7 @@ struct SchwarzData {
     double *ell_val = nullptr, *dinv0 = nullptr;
     double *part = nullptr;               // [nelv * 8]
     double *cv = nullptr;                 // [6][nv]: x, r, z, p0, p1, q
-    double *cpart = nullptr;              // [3][ceil(nv / 256)]
+    double *cpart = nullptr;              // [2 + sem_coarse_split()][ceil(nv / 256)]
     uint8_t *mult = nullptr;              // [n]
     // one-point overlap (built on first use): local operators on the element box
     // extended by one point beyond each face, and the face-neighbour table

@@ -562,15 +562,15 @@ __global__ __launch_bounds__(VT) void k_corner(CornerArgs A)
 // scalar kernel (the coarse system has only a few hundred partials).
 __device__ __forceinline__ double all_sum(const double *part, int64_t nblk, double *sh)
 {
-    if (threadIdx.x < 64) {
-        double s = 0.0;
-        for (int64_t q = threadIdx.x; q < nblk; q += 64) s += part[q];
+    double s = 0.0;
+    for (int64_t q = threadIdx.x; q < nblk; q += VT) s += part[q];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (threadIdx.x == 0) sh[0] = s;
-    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
-    const double v = sh[0];
+    double v = sh[0];
+#pragma unroll
+    for (int q = 1; q < VT / 64; ++q) v += sh[q];
     __syncthreads();
     return v;
 }
@@ -612,11 +612,17 @@ __global__ __launch_bounds__(VT) void k_ccg_start(CoarseArgs A)
 // Step it, first half: beta from the two latest (r, z) sums (it > 0), the new
 // direction p = z + beta p_old formed for the own row and, on the fly, for every
 // column the row touches; q = A p; partial of (p, q) into slot 2.  p alternates
-// between p0 (even steps) and p1 (odd steps).
-__global__ __launch_bounds__(VT) void k_ccg_spmv(CoarseArgs A, int it)
+// between p0 (even steps) and p1 (odd steps).  SPL lanes share a row (entries
+// w = part, part + SPL, ...; summed across the lanes in a fixed order), so a row's
+// gathers are split over SPL lanes; the grid is SPL times that of the other kernels
+// (g, the row-per-lane grid, passed in).
+#ifndef SEM_CCG_SPL
+#define SEM_CCG_SPL 4
+#endif
+constexpr int SPL = SEM_CCG_SPL;
+__global__ __launch_bounds__(VT) void k_ccg_spmv(CoarseArgs A, int it, int64_t g)
 {
     __shared__ double sh[VT / 64];
-    const int64_t g = gridDim.x;
     double beta = 0.0;
     if (it > 0) {
         const double rz = all_sum(A.partial + (it & 1) * g, g, sh);
@@ -625,20 +631,25 @@ __global__ __launch_bounds__(VT) void k_ccg_spmv(CoarseArgs A, int it)
     }
     double *pn = (it & 1) ? A.p1 : A.p0;
     const double *po = (it & 1) ? A.p0 : A.p1;
-    const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
+    const int part = threadIdx.x % SPL;
+    const int64_t v = ((int64_t)blockIdx.x * VT + threadIdx.x) / SPL;
     double pq = 0.0;
     if (v < A.nv) {
         double s = 0.0;
-        for (int w = 0; w < A.width; ++w) {
+        for (int w = part; w < A.width; w += SPL) {
             const int64_t k = (int64_t)w * A.nv + v;
             const int32_t c = A.ci[k];
             const double pc = (it > 0) ? fma(beta, po[c], A.z[c]) : A.z[c];
             s = fma(A.val[k], pc, s);
         }
-        const double pv = (it > 0) ? fma(beta, po[v], A.z[v]) : A.z[v];
-        pn[v] = pv;
-        A.q[v] = s;
-        pq = pv * s;
+#pragma unroll
+        for (int off = 1; off < SPL; off <<= 1) s += __shfl_xor(s, off, 64);
+        if (part == 0) {
+            const double pv = (it > 0) ? fma(beta, po[v], A.z[v]) : A.z[v];
+            pn[v] = pv;
+            A.q[v] = s;
+            pq = pv * s;
+        }
     }
     block_partial(pq, A.partial + 2 * g + blockIdx.x, sh);
 }
@@ -650,7 +661,7 @@ __global__ __launch_bounds__(VT) void k_ccg_update(CoarseArgs A, int it)
     __shared__ double sh[VT / 64];
     const int64_t g = gridDim.x;
     const double rz = all_sum(A.partial + (it & 1) * g, g, sh);
-    const double pq = all_sum(A.partial + 2 * g, g, sh);
+    const double pq = all_sum(A.partial + 2 * g, SPL * g, sh);
     const double alpha = (pq > 0.0 && isfinite(pq)) ? rz / pq : 0.0;
     const double *pn = (it & 1) ? A.p1 : A.p0;
     const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
@@ -1566,7 +1577,10 @@ hipError_t sem_launch_corner(const CornerArgs *A, hipStream_t st)
     return hipGetLastError();
 }
 // iters fixed-count Jacobi-CG steps on the coarse system from x = 0, two launches per
-// step and no host sync; partial must hold 3 * ceil(nv / VT) values.
+// step and no host sync; partial must hold (2 + SPL) * ceil(nv / VT) values.
+// lanes per row of the coarse SpMV (the coarse partial buffer is sized by it)
+int sem_coarse_split() { return SPL; }
+
 hipError_t sem_launch_coarse_cg(const CoarseArgs *A, int iters, hipStream_t st)
 {
     if (A->nv == 0) return hipSuccess;
@@ -1574,7 +1588,7 @@ hipError_t sem_launch_coarse_cg(const CoarseArgs *A, int iters, hipStream_t st)
     const unsigned g = (unsigned)((A->nv + VT - 1) / VT);
     hipLaunchKernelGGL(k_ccg_start, dim3(g), dim3(VT), 0, st, *A);
     for (int it = 0; it < iters; ++it) {
-        hipLaunchKernelGGL(k_ccg_spmv, dim3(g), dim3(VT), 0, st, *A, it);
+        hipLaunchKernelGGL(k_ccg_spmv, dim3(g * SPL), dim3(VT), 0, st, *A, it, (int64_t)g);
         hipLaunchKernelGGL(k_ccg_update, dim3(g), dim3(VT), 0, st, *A, it);
     }
     return hipGetLastError();
