@@ -662,6 +662,10 @@ def test_gmres_schwarz_overlap_vs_oracle():
     assert rel_inf(xh, xo) <= 1e-7
     with pytest.raises(sem.SemError, match="INVALID"):
         sem.gmres_solve(torch.zeros_like(b), b, P.coef, P.msh, P.Xh, P.gs, precond="schwarz", coarse_iters=-1)
+    P.coef.set_helmholtz(torch.ones(P.n, dtype=torch.float64, device=DEV), 0.0)
+    with pytest.raises(sem.SemError, match="UNSUPPORTED"):
+        P.gmres(b, rtol=1e-10, precond="schwarz_overlap")
+    P.coef.set_helmholtz(1.0, 0.0)
 
 
 # ------------------------------------------------------------------ projection (Section 4, Table 2)
