@@ -630,6 +630,36 @@ def test_schwarz_extension_matches_assembled_linear_segments():
             np.testing.assert_allclose(P._loc[e], ref, rtol=0, atol=1e-11 * np.abs(ref).max())
 
 
+def test_schwarz_local_operator_direction_lengths_on_a_stretched_box():
+    """On an undeformed box with a different element length per direction (1/2, 1/3, 1/4),
+    the separable local operator takes each direction's own length: it equals the
+    Kronecker form of three independent 1-D chain assemblies with those lengths, for the
+    element-only problem and for the one-point overlap (an interior element: the overlap
+    on all six faces).  A direction mix-up in the element lengths fails on this machine though
+    not on a cube."""
+    lx, h1, h2 = 5, 0.7, 3.0
+    nx, ny, nz = 3, 4, 5
+    lens = (1.0 / nx, 1.0 / ny, 1.0 / nz)
+    e = 1 + nx * (1 + ny * 1)                       # element (1, 1, 1): neighbours on all faces
+
+    def chains(overlap):
+        out = []
+        for L in lens:
+            _, _, x = _gll_element_1d(lx, L)
+            d1, d2 = x[1] - x[0], x[2] - x[1]
+            segs = [d1, d2] if overlap else [d1]
+            out.append(_chain_1d(lx, L, segs, segs))
+        return out
+
+    for overlap in (False, True):
+        P = oracle.Problem(nx, lx, 0.0, h1=h1, h2=h2, ny=ny, nz=nz).schwarz_setup(overlap=overlap)
+        (Kr, Mr), (Ks, Ms), (Kt, Mt) = chains(overlap)
+        ref = h1 * (np.kron(Mt, np.kron(Ms, Kr)) + np.kron(Mt, np.kron(Ks, Mr)) + np.kron(Kt, np.kron(Ms, Mr))) \
+            + h2 * np.kron(Mt, np.kron(Ms, Mr))
+        assert P._loc[e].shape == ref.shape
+        np.testing.assert_allclose(P._loc[e], ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
 def test_schwarz_overlap_local_operator_matches_assembled_chain():
     """One-point overlap: on an undeformed box the oracle's extended local operator is
     the Kronecker form built from independent 1-D chain assemblies -- beyond a face with
