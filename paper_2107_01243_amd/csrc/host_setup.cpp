@@ -371,7 +371,10 @@ bool face_neighbours(int64_t nelv, int lx, const int64_t *glb, std::vector<int32
             msg = "face_neighbours: a face is shared by more than two elements";
             return false;
         }
-        if (q2 - q == 2 && (!link(rec[q].ef, rec[q + 1].ef) || !link(rec[q + 1].ef, rec[q].ef))) {
+        // an element holding both copies of a face (periodic, one element across) is not
+        // its own neighbour
+        if (q2 - q == 2 && rec[q].ef / 6 != rec[q + 1].ef / 6 &&
+            (!link(rec[q].ef, rec[q + 1].ef) || !link(rec[q + 1].ef, rec[q].ef))) {
             msg = "face_neighbours: two elements share a face's corners but not its points as a grid";
             return false;
         }

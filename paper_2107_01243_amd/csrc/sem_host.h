@@ -45,7 +45,8 @@ void element_order(const GsMaps &m, std::vector<int32_t> &pairs, std::vector<int
 // {e2, base, sa, sb}: e2 the other element holding the face (every point of it, at
 // matching grid positions), and, for face point (fa, fb), base + fa sa + fb sb the
 // local index in e2 of the point one GLL index inside e2 from that point's copy;
-// e2 = -1 (and zeros) where no other element holds the face.  Returns false (msg
+// e2 = -1 (and zeros) where no other element holds the face (an element holding both
+// copies of a periodic face is not its own neighbour).  Returns false (msg
 // set) when a face is held by more than two elements or two elements share a face's
 // corners but not its points.
 bool face_neighbours(int64_t nelv, int lx, const int64_t *glb, std::vector<int32_t> &out, std::string &msg);

@@ -203,6 +203,14 @@ static void check_faces_invalid()
     msg.clear();
     CHECK(!semh::face_neighbours(2, lx, two.data(), fn, msg), "mismatched face interior accepted");
     CHECK(msg.find("not its points") != std::string::npos, "message: %s", msg.c_str());
+    // one element, periodic in r (the i = lx - 1 face takes the ids of the i = 0 face): no
+    // neighbour on either face
+    std::vector<int64_t> per(one);
+    for (int k = 0; k < lx; ++k)
+        for (int j = 0; j < lx; ++j) per[(lx - 1) + lx * (j + lx * k)] = per[0 + lx * (j + lx * k)];
+    msg.clear();
+    CHECK(semh::face_neighbours(1, lx, per.data(), fn, msg), "%s", msg.c_str());
+    CHECK(fn[0] == -1 && fn[4] == -1, "periodic self-neighbour: %d %d", fn[0], fn[4]);
 }
 
 int main()
