@@ -11,7 +11,10 @@ GMRES (``Problem.gmres``) are written here with numpy on top of the C operator
 (small dense systems solved by ``numpy.linalg``).
 
 Every function cites the passage of the paper it follows; the readings taken
-where the paper is silent or garbled are listed at the top of ``sem_oracle.c``.
+where the paper is silent or garbled are listed at the top of ``sem_oracle.c`` for
+the C part, and in the docstrings of ``projection``, ``gmres`` and
+``schwarz_setup`` (element lengths, extension segments, the one-point overlap,
+the coarse space and its fixed-count solve) for the numpy part.
 """
 from __future__ import annotations
 
