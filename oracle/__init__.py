@@ -6,9 +6,10 @@ It shares no code with the HIP path.  The arithmetic lives in
 ``sem_oracle.c`` (plain loops, FP64, ``-O2 -ffp-contract=off``); this module
 only marshals numpy arrays into it.
 
-The projection onto previous solutions (``Problem.projection``) and flexible
-GMRES (``Problem.gmres``) are written here with numpy on top of the C operator
-(small dense systems solved by ``numpy.linalg``).
+The projection onto previous solutions (``Problem.projection``), flexible GMRES
+(``Problem.gmres``) and the two-level Schwarz preconditioner
+(``Problem.schwarz_setup`` / ``schwarz_apply``) are written here with numpy on top
+of the C operator (small dense systems solved by ``numpy.linalg``).
 
 Every function cites the passage of the paper it follows; the readings taken
 where the paper is silent or garbled are listed at the top of ``sem_oracle.c`` for
