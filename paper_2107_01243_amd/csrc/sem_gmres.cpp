@@ -298,6 +298,9 @@ static sem_status schwarz_setup_overlap(sem_coef c, hipStream_t st)
             }
         }
     }, 64);
+    dfree(Z.S_ov);  // left by an earlier setup that failed part way
+    dfree(Z.lam_ov);
+    dfree(Z.face);
     SEM_TRY(dalloc(&Z.S_ov, S.size()));
     SEM_TRY(dalloc(&Z.lam_ov, lam.size()));
     SEM_TRY(dalloc(&Z.face, face.size()));
